@@ -1,0 +1,106 @@
+"""Pins of the analytic sphere solutions (sections 4.2 and 4.3)."""
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import spherical_jn
+
+from oracle import mie
+
+
+def test_wronskian():
+    for k in (0.7, 5.0, 50.0):
+        l = np.arange(0, int(k) + 20)
+        j, jp = spherical_jn(l, k), spherical_jn(l, k, True)
+        h, hp = mie.sph_hankel1(l, k), mie.sph_hankel1(l, k, True)
+        assert np.allclose(j * hp - jp * h, 1j / k**2, rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("k", [2.0, 5.0, 20.0])
+def test_mie_satisfies_neumann_condition(k):
+    ct = np.cos(np.linspace(0, np.pi, 13))
+    h = 1e-5
+    up = mie.mie_hard_total_field(k, np.full(ct.shape, 1 + h), ct)
+    um = mie.mie_hard_total_field(k, np.full(ct.shape, 1 + 2 * h), ct)
+    u0 = mie.mie_hard_total_field(k, np.ones_like(ct), ct)
+    dudr = (-3 * u0 + 4 * up - um) / (2 * h)
+    assert np.max(np.abs(dudr)) < 1e-6 * k * np.max(np.abs(u0)) * 50
+    # on the surface the series equals the compact surface form
+    assert np.allclose(u0, mie.mie_hard_total_surface(k, ct), rtol=1e-10, atol=1e-12)
+
+
+def test_mie_paper_series_form():
+    """u = u_inc + sum_m [-i^m (2m+1) j'_m/h'_m] h_m P_m on r = 1 (section 4.3)."""
+    k = 5.0
+    ct = np.cos(np.linspace(0, np.pi, 9))
+    L = mie.default_lmax(k)
+    l = np.arange(L + 1)
+    coef = -(1j ** l) * (2 * l + 1) * spherical_jn(l, k, True) / mie.sph_hankel1(l, k, True) * mie.sph_hankel1(l, k)
+    us = coef @ mie.legendre_table(L, ct)
+    u = np.exp(1j * k * ct) + us
+    assert np.allclose(u, mie.mie_hard_total_surface(k, ct), rtol=1e-12, atol=1e-12)
+
+
+def test_mie_far_field_is_outgoing():
+    k, ct = 3.0, np.array([0.3])
+    r1, r2 = 200.0, 200.0 + np.pi / k
+    us1 = mie.mie_hard_scattered(k, np.array([r1]), ct)
+    us2 = mie.mie_hard_scattered(k, np.array([r2]), ct)
+    # the scattered part of the full series at moderate r matches
+    rr = np.array([1.7])
+    assert np.allclose(mie.mie_hard_total_field(k, rr, ct) - np.exp(1j * k * rr * ct),
+                       mie.mie_hard_scattered(k, rr, ct), rtol=1e-10)
+    # exp(ikr)/r: half a wavelength further the value flips sign and scales r1/r2
+    assert abs(us2 / us1 + r1 / r2) < 1e-2
+
+
+def _single_layer_quad(k, l):
+    """Apply S to P_l(cos t) at the north pole by 2-D quadrature."""
+    def f(phi, t, part):
+        y = np.array([np.sin(t) * np.cos(phi), np.sin(t) * np.sin(phi), np.cos(t)])
+        r = np.linalg.norm(np.array([0, 0, 1.0]) - y)
+        v = np.exp(1j * k * r) / (4 * np.pi * r) * mie.legendre_table(l, np.array([np.cos(t)]))[l, 0] * np.sin(t)
+        return v.real if part == 0 else v.imag
+    re = integrate.dblquad(lambda p, t: f(p, t, 0), 0, np.pi, 0, 2 * np.pi, epsabs=1e-11, epsrel=1e-11)[0]
+    im = integrate.dblquad(lambda p, t: f(p, t, 1), 0, np.pi, 0, 2 * np.pi, epsabs=1e-11, epsrel=1e-11)[0]
+    return re + 1j * im
+
+
+def _double_layer_quad(k, l, r0=1.0):
+    """Apply D (normal into the body, n_y = -y) at x = (0,0,r0)."""
+    x = np.array([0, 0, r0])
+
+    def f(t, part):
+        # axisymmetric: integrate over phi analytically by quadrature inside
+        def g(phi):
+            y = np.array([np.sin(t) * np.cos(phi), np.sin(t) * np.sin(phi), np.cos(t)])
+            d = x - y
+            r = np.linalg.norm(d)
+            G = np.exp(1j * k * r) / (4 * np.pi * r)
+            return G * (1 / r - 1j * k) * (d @ (-y)) / r
+        v = integrate.quad(lambda p: g(p).real, 0, 2 * np.pi, epsabs=1e-12)[0] + 1j * integrate.quad(lambda p: g(p).imag, 0, 2 * np.pi, epsabs=1e-12)[0]
+        v *= mie.legendre_table(l, np.array([np.cos(t)]))[l, 0] * np.sin(t)
+        return v.real if part == 0 else v.imag
+    pts = [0.0, 1e-3, 1e-2, 0.1, np.pi]
+    re = sum(integrate.quad(lambda t: f(t, 0), a, b, epsabs=1e-11, limit=200)[0] for a, b in zip(pts[:-1], pts[1:]))
+    im = sum(integrate.quad(lambda t: f(t, 1), a, b, epsabs=1e-11, limit=200)[0] for a, b in zip(pts[:-1], pts[1:]))
+    return re + 1j * im
+
+
+@pytest.mark.parametrize("l", [0, 2])
+def test_sphere_spectra_S_and_D_by_quadrature(l):
+    k = 2.0
+    sp_ = mie.sphere_spectra(k, l)
+    assert abs(_single_layer_quad(k, l) - sp_["S"]) < 1e-7
+    assert abs(_double_layer_quad(k, l) - sp_["D"]) < 1e-6
+
+
+def test_pulsating_sphere_from_spectra():
+    """Neumann data q = 1: (1/2 + D) u = (S + alpha M) q - alpha q / 2 on the
+    l = 0 mode gives the closed form u = 1/(1 - ik) (section 4.2)."""
+    for k in (2 * np.pi, 4 * np.pi, 3.3):
+        s = mie.sphere_spectra(k, 0)
+        a = 1j / k
+        u = (s["S"] + a * s["M"] - 0.5 * a) / s["BM"]
+        assert abs(u - mie.pulsating_sphere(k)) < 1e-12
+        # CBIE alone is singular at the characteristic frequencies k = n pi
+    assert abs(mie.sphere_spectra(2 * np.pi, 0)["CBIE"]) < 1e-12
