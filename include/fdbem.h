@@ -1,0 +1,146 @@
+/*
+ * fdbem -- fast directional Burton-Miller boundary element mat-vec and solver
+ * for AMD Instinct MI355X (gfx950).  Public C ABI.
+ *
+ * Method: Cao, Wen, Xiao, Liu, "A fast directional BEM for large-scale
+ * acoustic problems based on the Burton-Miller formulation" (arXiv 1311.5202).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Complex vectors are arrays of interleaved FP64 pairs (re, im), i.e.
+ *    C99 "double complex" / torch.complex128, length N, in the CALLER's node
+ *    order.  Device pointers ("_dev") must point to memory on the current HIP
+ *    device; host pointers are read during the call only.
+ *  - The plan owns every device allocation it makes; the caller owns the
+ *    input/output buffers.  Calls are ordered on the HIP stream passed in
+ *    (NULL = the default stream) and do not synchronise unless stated.
+ *  - Normals point INTO the body (out of the acoustic domain): the orientation
+ *    under which the integral representation of section 2.1 carries +dG/dn_y.
+ *  - alpha = i/k (section 2.1, eq. eq_bm).
+ *  - Return value: FDA_OK (0) or a negative FDA_E* code; nothing is thrown
+ *    across the ABI.  fda_last_error() returns a thread-local message for the
+ *    last failing call on the calling thread.
+ */
+#ifndef FDBEM_H
+#define FDBEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FDA_OK = 0,
+    FDA_EINVAL = -1,        /* bad argument (sizes, k <= 0, eps outside (0,1), null pointer) */
+    FDA_ENOMEM = -2,        /* host or device allocation failed */
+    FDA_EHIP = -3,          /* a HIP runtime call failed */
+    FDA_NOT_CONVERGED = -4, /* GMRES reached maxit; x holds the last iterate */
+    FDA_NONFINITE = -5,     /* NaN/Inf in an input vector or in the Krylov recurrence */
+    FDA_EBREAKDOWN = -6,    /* GMRES breakdown before the tolerance was met */
+    FDA_ENOTSUP = -7        /* option combination not supported */
+};
+
+/* Operators applied by fda_matvec (section 2.2 eqs. eq_hmat, eq_gmat, kcorrection,
+ * section 4.1 eq. eq_sum).  w_j are the quadrature weights of the geometry. */
+enum {
+    FDA_OP_RAW_H = 0,  /* p_i = sum_{j!=i} w_j [dG/dn_y + alpha d2G/dn_x dn_y](x_i,y_j) u_j */
+    FDA_OP_RAW_G = 1,  /* p_i = sum_{j!=i} w_j [G + alpha dG/dn_x](x_i,y_j) u_j              */
+    FDA_OP_RAW_T1 = 2, /* p_i = sum_{j!=i} w_j [G + alpha dG/dn_y](x_i,y_j) u_j (eq. eq_sum)  */
+    FDA_OP_BM_H = 3,   /* (1/2) u_i + sum_j Hbar_ij u_j: the sound-hard Burton-Miller operator,
+                          raw H sum plus the locally corrected near field (needs elements)   */
+    FDA_OP_BM_G = 4    /* sum_j Gbar_ij q_j: corrected G sum (needs elements)                */
+};
+
+enum { FDA_PREC_FP64 = 0, FDA_PREC_FP32 = 1 };
+
+/* Geometry: Nystrom nodes with normals and weights; optionally the curved
+ * quadratic elements they come from (needed for the local corrections).
+ * Element e holds 6 geometric nodes (corners 0,1,2 counter-clockwise seen
+ * from the acoustic side, then mid-edge nodes of edges 01, 12, 20), 18
+ * doubles, and owns nodes 6e..6e+5 in the order of bem_nystrom_nodes. */
+typedef struct {
+    int64_t n_nodes;
+    const double *pts; /* n_nodes x 3 */
+    const double *nrm; /* n_nodes x 3, unit, into the body */
+    const double *w;   /* n_nodes */
+    int64_t n_elem;    /* 0, or n_nodes / 6 */
+    const double *elem;/* n_elem x 6 x 3, or NULL */
+} fda_geometry;
+
+typedef struct {
+    double svd_eps;     /* truncation of the pseudo-inverses (eq. eq_invr); 0 -> eps      */
+    double lowrank_eps; /* truncation of the low-rank M2L factors (eq. eq_lrdk); 0 -> eps */
+    int leaf_cap;       /* max points per octree leaf; 0 -> 64                            */
+    int leaf_rule;      /* 0: leaves are low-frequency cubes (w < lambda)                  */
+    double c_d;         /* high-frequency near-field constant (section 3.1.1); 0 -> 1/pi  */
+    int far_field;      /* 1: fast directional far field; 0: all pairs summed directly    */
+    int lf_grid;        /* points per edge of low-frequency surface grids; 0 -> from eps  */
+    int precision;      /* FDA_PREC_FP64 or FDA_PREC_FP32 (far field and P2P in FP32)     */
+    int corrections;    /* 1: build the local corrections when elements are given        */
+    int verbose;
+} fda_opts;
+
+typedef struct fda_plan fda_plan;
+
+/* Fill *o with the defaults listed above. */
+int fda_default_opts(fda_opts *o);
+
+/* Nystrom discretisation (section 2.2): nodes, unit normals (into the body)
+ * and weights of the six-point degree-4 Gauss rule on each curved quadratic
+ * element.  All host arrays; pts/nrm are 6*n_elem x 3, w is 6*n_elem. */
+int bem_nystrom_nodes(int64_t n_elem, const double *elem, double *pts, double *nrm, double *w);
+
+/* Build a plan on the current HIP device: octree and lists (section 3.1.1),
+ * point templates and pseudo-inverses (section 3.1.2, eqs. eq_svdr/eq_invr),
+ * compressed translation operators (section 4.1, eqs. eq_cmps..eq_cmpt),
+ * low-rank M2L factors (eq. eq_lrdk) and, with elements, the locally
+ * corrected near field (section 2.2).  k > 0 is the wavenumber, eps in
+ * (0,1) the controlling accuracy.  opts may be NULL (defaults).  Host work
+ * is FP64; everything the mat-vec reads is uploaded.  Synchronous. */
+int fda_build(const fda_geometry *geom, double k, double eps, const fda_opts *opts, fda_plan **out);
+
+/* out_dev = Op(in_dev) for op in FDA_OP_*: both complex128[N] device
+ * buffers in caller order (they must not overlap).  BM_* ops need a plan
+ * built with elements.  Stream-ordered, no synchronisation. */
+int fda_matvec(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *hip_stream);
+
+/* Solve Op x = rhs by GMRES (section 2.2 eq. Axb; right preconditioned,
+ * x0 = 0, restart length `restart`, Arnoldi by classical Gram-Schmidt with
+ * re-orthogonalisation, FP64).  Stops when ||b - A x|| / ||b|| <= tol.
+ * rhs_dev/x_dev: complex128[N] device buffers.  iters_out, relres_out may be
+ * NULL; resid_hist (host, maxit+1 doubles) may be NULL.  precond: 0 none,
+ * 1 block-Jacobi on the corrected near-field leaf blocks.  Synchronises the
+ * stream once per iteration.  FDA_NOT_CONVERGED leaves the last iterate. */
+int bm_solve(fda_plan *plan, int op, const void *rhs_dev, double tol, int maxit, int restart, int precond,
+             void *x_dev, int *iters_out, double *relres_out, double *resid_hist, void *hip_stream);
+
+/* Right-hand side of the sound-hard problem (section 4.3): incident plane
+ * wave u_inc = exp(i k x.d) with unit direction d[3];
+ * b_i = u_inc(x_i) + alpha du_inc/dn_x(x_i).  rhs_dev: complex128[N]. */
+int fda_rhs_plane_wave(fda_plan *plan, const double d[3], void *rhs_dev, void *hip_stream);
+
+/* JSON description of the plan (levels, slot counts, ranks, memory, set-up
+ * and per-phase timings of the last timed mat-vec).  Writes at most len bytes
+ * including the terminating zero; returns FDA_EINVAL if it does not fit. */
+int fda_stats(const fda_plan *plan, char *json_buf, size_t len);
+
+/* Enable (1) or disable (0) per-phase HIP-event timing of fda_matvec. */
+int fda_set_timing(fda_plan *plan, int on);
+
+/* Per-phase times (milliseconds) of the last timed mat-vec, in the order
+ * P2P, S2M, M2M, M2L, L2L, L2T, near correction, permutations.  n: capacity. */
+int fda_phase_times(const fda_plan *plan, double *ms, int n);
+
+/* Release every device and host resource of the plan (NULL is allowed). */
+void fda_destroy(fda_plan *plan);
+
+/* Message of the last non-zero status on this thread ("" if none). */
+const char *fda_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDBEM_H */

@@ -1,0 +1,211 @@
+// C ABI of the library (declared in include/fdbem.h).  Every entry point
+// catches exceptions and turns them into status codes.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/fdbem.h"
+#include "device.hpp"
+
+namespace fdbem {
+Plan *plan_create_host(int64_t n, const double *pts, const double *nrm, const double *w, int64_t n_elem,
+                       const double *elem, double k, double eps, const Options &opt);
+std::string plan_stats(const Plan &P);
+}  // namespace fdbem
+
+using namespace fdbem;
+
+struct fda_plan {
+    Plan *P;
+};
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+template <typename F>
+static int guarded(F &&f)
+{
+    try {
+        g_err.clear();
+        return f();
+    } catch (const std::invalid_argument &e) {
+        return fail(FDA_EINVAL, e.what());
+    } catch (const std::bad_alloc &e) {
+        return fail(FDA_ENOMEM, "out of host memory");
+    } catch (const std::runtime_error &e) {
+        const std::string m = e.what();
+        if (m.find("hipErrorOutOfMemory") != std::string::npos || m.find("out of memory") != std::string::npos)
+            return fail(FDA_ENOMEM, m);
+        if (m.find("HIP error") != std::string::npos) return fail(FDA_EHIP, m);
+        return fail(FDA_ENOTSUP, m);
+    } catch (...) {
+        return fail(FDA_EHIP, "unknown error");
+    }
+}
+
+extern "C" {
+
+int fda_default_opts(fda_opts *o)
+{
+    if (!o) return fail(FDA_EINVAL, "null options");
+    Options d;
+    o->svd_eps = 0;
+    o->lowrank_eps = 0;
+    o->leaf_cap = d.leaf_cap;
+    o->leaf_rule = d.leaf_rule;
+    o->c_d = d.c_d;
+    o->far_field = d.far_field;
+    o->lf_grid = 0;
+    o->precision = FDA_PREC_FP64;
+    o->corrections = 1;
+    o->verbose = 0;
+    return FDA_OK;
+}
+
+int bem_nystrom_nodes(int64_t n_elem, const double *elem, double *pts, double *nrm, double *w)
+{
+    return guarded([&] {
+        if (n_elem <= 0 || !elem || !pts || !nrm || !w) throw std::invalid_argument("bad nystrom arguments");
+        nystrom_nodes(n_elem, elem, pts, nrm, w);
+        return FDA_OK;
+    });
+}
+
+int fda_build(const fda_geometry *g, double k, double eps, const fda_opts *o, fda_plan **out)
+{
+    return guarded([&] {
+        if (!g || !out) throw std::invalid_argument("null geometry or output pointer");
+        *out = nullptr;
+        Options opt;
+        if (o) {
+            opt.svd_eps = o->svd_eps;
+            opt.lowrank_eps = o->lowrank_eps;
+            opt.leaf_cap = o->leaf_cap > 0 ? o->leaf_cap : 64;
+            opt.leaf_rule = o->leaf_rule;
+            opt.c_d = o->c_d > 0 ? o->c_d : opt.c_d;
+            opt.far_field = o->far_field;
+            opt.lf_grid = o->lf_grid;
+            opt.precision = o->precision;
+            opt.corrections = o->corrections;
+            opt.verbose = o->verbose;
+        }
+        if (opt.precision != FDA_PREC_FP64) throw std::invalid_argument("precision not available in this build");
+        if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");
+        Plan *P = plan_create_host(g->n_nodes, g->pts, g->nrm, g->w, g->n_elem, g->elem, k, eps, opt);
+        try {
+            device_upload(*P);
+        } catch (...) {
+            device_free(*P);
+            delete P;
+            throw;
+        }
+        fda_plan *h = new fda_plan{P};
+        *out = h;
+        return FDA_OK;
+    });
+}
+
+int fda_matvec(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *stream)
+{
+    return guarded([&] {
+        if (!plan || !in_dev || !out_dev) throw std::invalid_argument("null argument");
+        if (op < FDA_OP_RAW_H || op > FDA_OP_BM_G) throw std::invalid_argument("unknown operator");
+        if (in_dev == out_dev) throw std::invalid_argument("input and output must not alias");
+        Plan &P = *plan->P;
+        if ((op == FDA_OP_BM_H || op == FDA_OP_BM_G) && !P.has_corr)
+            throw std::invalid_argument("Burton-Miller operators need a plan built with elements");
+        if (op == FDA_OP_BM_G) throw std::runtime_error("corrected G operator not available in this build");
+        device_matvec(P, op, (const double2 *)in_dev, (double2 *)out_dev, (hipStream_t)stream);
+        return FDA_OK;
+    });
+}
+
+int bm_solve(fda_plan *plan, int op, const void *rhs_dev, double tol, int maxit, int restart, int precond,
+             void *x_dev, int *iters_out, double *relres_out, double *resid_hist, void *stream)
+{
+    return guarded([&] {
+        if (!plan || !rhs_dev || !x_dev) throw std::invalid_argument("null argument");
+        if (!(tol > 0) || maxit < 1 || restart < 1) throw std::invalid_argument("bad solver parameters");
+        if (op < FDA_OP_RAW_H || op > FDA_OP_BM_G) throw std::invalid_argument("unknown operator");
+        Plan &P = *plan->P;
+        if ((op == FDA_OP_BM_H || op == FDA_OP_BM_G) && !P.has_corr)
+            throw std::invalid_argument("Burton-Miller operators need a plan built with elements");
+        const int rc = device_gmres(P, op, (const double2 *)rhs_dev, tol, maxit, restart, precond, (double2 *)x_dev,
+                                    iters_out, relres_out, resid_hist, (hipStream_t)stream);
+        if (rc == FDA_NOT_CONVERGED) return fail(rc, "GMRES did not reach the tolerance");
+        if (rc == FDA_NONFINITE) return fail(rc, "non-finite value in GMRES");
+        if (rc == FDA_EBREAKDOWN) return fail(rc, "GMRES breakdown");
+        if (rc == FDA_ENOTSUP) return fail(rc, "preconditioner not available");
+        return rc;
+    });
+}
+
+int fda_rhs_plane_wave(fda_plan *plan, const double d[3], void *rhs_dev, void *stream)
+{
+    return guarded([&] {
+        if (!plan || !d || !rhs_dev) throw std::invalid_argument("null argument");
+        const double n2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (!(n2 > 0)) throw std::invalid_argument("zero direction");
+        const double s = 1.0 / std::sqrt(n2);
+        const double dd[3] = {d[0] * s, d[1] * s, d[2] * s};
+        device_rhs_plane_wave(*plan->P, dd, (double2 *)rhs_dev, (hipStream_t)stream);
+        return FDA_OK;
+    });
+}
+
+int fda_stats(const fda_plan *plan, char *buf, size_t len)
+{
+    return guarded([&] {
+        if (!plan || !buf) throw std::invalid_argument("null argument");
+        const Plan &P = *plan->P;
+        std::string s = plan_stats(P);
+        s.pop_back();  // strip the closing brace to append device figures
+        s += ", \"device_bytes\": " + std::to_string(P.dev ? P.dev->bytes : 0) + ", \"phase_ms\": [";
+        for (int t = 0; t < 8; ++t) s += (t ? ", " : "") + std::to_string(P.dev ? P.dev->phase_ms[t] : 0.0);
+        s += "]}";
+        if (s.size() + 1 > len) throw std::invalid_argument("stats buffer too small");
+        std::memcpy(buf, s.c_str(), s.size() + 1);
+        return FDA_OK;
+    });
+}
+
+int fda_set_timing(fda_plan *plan, int on)
+{
+    return guarded([&] {
+        if (!plan) throw std::invalid_argument("null plan");
+        plan->P->dev->timing = on ? 1 : 0;
+        return FDA_OK;
+    });
+}
+
+int fda_phase_times(const fda_plan *plan, double *ms, int n)
+{
+    return guarded([&] {
+        if (!plan || !ms || n < 0) throw std::invalid_argument("null argument");
+        for (int t = 0; t < n && t < 8; ++t) ms[t] = plan->P->dev->phase_ms[t];
+        return FDA_OK;
+    });
+}
+
+void fda_destroy(fda_plan *plan)
+{
+    if (!plan) return;
+    try {
+        device_free(*plan->P);
+    } catch (...) {
+    }
+    delete plan->P;
+    delete plan;
+}
+
+const char *fda_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

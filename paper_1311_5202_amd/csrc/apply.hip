@@ -1,0 +1,598 @@
+// HIP kernels and launch sequence of the fast directional Burton-Miller
+// mat-vec (paper sections 3.1.2 and 3.2) for gfx950.
+//
+// One mat-vec, all stream-ordered:
+//   permute + weight  s_j = w_j u_perm(j)                  (sorted order)
+//   P2P               near field, direct kernel sums        (section 3.2, modification 3)
+//   S2M               check potentials of leaf sources, then W = S~^-1 U~^H
+//                     (E_up = dG/dn_y for the H sum: modification 1)
+//   M2M               bottom-up, compressed M~ per (level, wedge, octant)
+//   M2L               per level, K~ or its low-rank factors U^ (V^ x)
+//   L2L               top-down, L~ = M~^T
+//   L2T               W^T y gives incoming equivalent densities, then
+//                     E_dn = G + alpha dG/dn_x at the targets (modification 2)
+//   un-permute, free term, near-field correction SpMV (caller order)
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+#include "device.hpp"
+
+namespace fdbem {
+
+#define HIP_CHECK(expr)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            throw std::runtime_error(std::string("HIP error ") + hipGetErrorString(e_) + " at " + \
+                                     __FILE__ + ":" + std::to_string(__LINE__));                 \
+    } while (0)
+
+struct OpC {
+    double2 cd00, cd10, cd01, cd11;  // products c_a d_b of K = (c0 + c1 d/dn_y)(d0 + d1 d/dn_x) G
+    double2 c0, c1, d0, d1;
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
+
+// Full kernel K(x <- y) with normals at both ends.
+__device__ __forceinline__ double2 kernel_full(double dx, double dy, double dz, double nxx, double nxy, double nxz,
+                                               double nyx, double nyy, double nyz, double k, const OpC &c)
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r = sqrt(r2);
+    const double ir = 1.0 / r;
+    double sn, cs;
+    sincos(k * r, &sn, &cs);
+    const double g = ir * kInv4Pi;
+    const double2 G = make_double2(cs * g, sn * g);
+    const double dnx = (dx * nxx + dy * nxy + dz * nxz) * ir;  // (d.n_x)/r
+    const double dny = (dx * nyx + dy * nyy + dz * nyz) * ir;  // (d.n_y)/r
+    const double nn = nxx * nyx + nxy * nyy + nxz * nyz;
+    const double2 a = make_double2(ir, -k);                     // 1/r - ik
+    const double2 q = make_double2(k * k - 3.0 * ir * ir, 3.0 * k * ir);
+    double2 t = c.cd00;
+    t = cadd(t, cmul(c.cd10, cscale(a, dny)));
+    t = cadd(t, cmul(c.cd01, cscale(a, -dnx)));
+    const double2 hx = cadd(cscale(q, dnx * dny), cscale(a, nn * ir));
+    t = cadd(t, cmul(c.cd11, hx));
+    return cmul(G, t);
+}
+
+// Source-side kernel (c0 + c1 d/dn_y) G at a point x without normal.
+__device__ __forceinline__ double2 kernel_src(double dx, double dy, double dz, double nyx, double nyy, double nyz,
+                                              double k, const OpC &c)
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r = sqrt(r2);
+    const double ir = 1.0 / r;
+    double sn, cs;
+    sincos(k * r, &sn, &cs);
+    const double g = ir * kInv4Pi;
+    const double2 G = make_double2(cs * g, sn * g);
+    const double dny = (dx * nyx + dy * nyy + dz * nyz) * ir;
+    const double2 a = make_double2(ir, -k);
+    return cmul(G, cadd(c.c0, cmul(c.c1, cscale(a, dny))));
+}
+
+// Target-side kernel (d0 + d1 d/dn_x) G from a point y without normal.
+__device__ __forceinline__ double2 kernel_tgt(double dx, double dy, double dz, double nxx, double nxy, double nxz,
+                                              double k, const OpC &c)
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r = sqrt(r2);
+    const double ir = 1.0 / r;
+    double sn, cs;
+    sincos(k * r, &sn, &cs);
+    const double g = ir * kInv4Pi;
+    const double2 G = make_double2(cs * g, sn * g);
+    const double dnx = (dx * nxx + dy * nxy + dz * nxz) * ir;
+    const double2 a = make_double2(ir, -k);
+    return cmul(G, cadd(c.d0, cmul(c.d1, cscale(a, -dnx))));
+}
+
+// ---------------------------------------------------------------- kernels
+__global__ void k_fill_zero(double2 *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_permute_in(const double2 *__restrict__ in, const int64_t *__restrict__ perm,
+                             const double *__restrict__ w, double2 *__restrict__ dens, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dens[i] = cscale(in[perm[i]], w[i]);
+}
+
+__global__ void k_permute_out(const double2 *__restrict__ res, const int64_t *__restrict__ perm,
+                              const double2 *__restrict__ in, double free_term, double2 *__restrict__ out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = perm[i];
+    double2 v = res[i];
+    if (free_term != 0.0) v = cadd(v, cscale(in[j], free_term));
+    out[j] = v;
+}
+
+// Near field: one 64-lane wavefront per target leaf; sources staged in LDS.
+constexpr int P2P_TILE = 64;
+__global__ __launch_bounds__(P2P_TILE) void k_p2p(const int64_t *__restrict__ ts, const int64_t *__restrict__ te,
+                                                  const int *__restrict__ ptr, const int64_t *__restrict__ ss,
+                                                  const int64_t *__restrict__ se, const double *__restrict__ X,
+                                                  const double *__restrict__ Y, const double *__restrict__ Z,
+                                                  const double *__restrict__ NX, const double *__restrict__ NY,
+                                                  const double *__restrict__ NZ, const double2 *__restrict__ dens,
+                                                  double2 *__restrict__ res, double k, OpC c)
+{
+    __shared__ double sx[P2P_TILE], sy[P2P_TILE], sz[P2P_TILE], snx[P2P_TILE], sny[P2P_TILE], snz[P2P_TILE];
+    __shared__ double2 sd[P2P_TILE];
+    const int leaf = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t t0 = ts[leaf], t1 = te[leaf];
+    const int e0 = ptr[leaf], e1 = ptr[leaf + 1];
+    for (int64_t ib = t0; ib < t1; ib += P2P_TILE) {
+        const int64_t i = ib + tid;
+        const bool act = i < t1;
+        double xi = 0, yi = 0, zi = 0, nxi = 0, nyi = 0, nzi = 0;
+        if (act) {
+            xi = X[i];
+            yi = Y[i];
+            zi = Z[i];
+            nxi = NX[i];
+            nyi = NY[i];
+            nzi = NZ[i];
+        }
+        double2 acc = make_double2(0.0, 0.0);
+        for (int e = e0; e < e1; ++e) {
+            const int64_t s0 = ss[e], s1 = se[e];
+            for (int64_t jb = s0; jb < s1; jb += P2P_TILE) {
+                __syncthreads();
+                const int64_t j = jb + tid;
+                if (j < s1) {
+                    sx[tid] = X[j];
+                    sy[tid] = Y[j];
+                    sz[tid] = Z[j];
+                    snx[tid] = NX[j];
+                    sny[tid] = NY[j];
+                    snz[tid] = NZ[j];
+                    sd[tid] = dens[j];
+                }
+                __syncthreads();
+                const int cnt = (int)((s1 - jb) < P2P_TILE ? (s1 - jb) : P2P_TILE);
+                if (act) {
+                    for (int q = 0; q < cnt; ++q) {
+                        if (jb + q == i) continue;
+                        const double2 K = kernel_full(xi - sx[q], yi - sy[q], zi - sz[q], nxi, nyi, nzi, snx[q],
+                                                      sny[q], snz[q], k, c);
+                        acc = cadd(acc, cmul(K, sd[q]));
+                    }
+                }
+            }
+        }
+        if (act) res[i] = acc;
+    }
+}
+
+// S2M: check potentials of the leaf's sources at the level's check points
+// (template + leaf centre), then x = W phi written to the outgoing slot.
+constexpr int LEAF_BLOCK = 256;
+__global__ __launch_bounds__(LEAF_BLOCK) void k_s2m(const int64_t *__restrict__ start, const int64_t *__restrict__ end,
+                                                    const int64_t *__restrict__ slot, const int *__restrict__ tmpl,
+                                                    const double *__restrict__ center, const int *__restrict__ t_s,
+                                                    const int *__restrict__ t_ny, const int64_t *__restrict__ t_yoff,
+                                                    const int64_t *__restrict__ t_woff, const double *__restrict__ tY,
+                                                    const double2 *__restrict__ tW, const double *__restrict__ X,
+                                                    const double *__restrict__ Y, const double *__restrict__ Z,
+                                                    const double *__restrict__ NX, const double *__restrict__ NY,
+                                                    const double *__restrict__ NZ, const double2 *__restrict__ dens,
+                                                    double2 *__restrict__ od, double k, OpC c)
+{
+    extern __shared__ double2 phi[];
+    const int task = blockIdx.x, tid = threadIdx.x;
+    const int lev = tmpl[task];
+    const int s = t_s[lev], ny = t_ny[lev];
+    const double *Yt = tY + t_yoff[lev];
+    const double2 *W = tW + t_woff[lev];
+    const double cx = center[3 * task], cy = center[3 * task + 1], cz = center[3 * task + 2];
+    const int64_t j0 = start[task], j1 = end[task];
+    for (int a = tid; a < ny; a += LEAF_BLOCK) {
+        const double ax = cx + Yt[3 * a], ay = cy + Yt[3 * a + 1], az = cz + Yt[3 * a + 2];
+        double2 acc = make_double2(0.0, 0.0);
+        for (int64_t j = j0; j < j1; ++j) {
+            const double2 K = kernel_src(ax - X[j], ay - Y[j], az - Z[j], NX[j], NY[j], NZ[j], k, c);
+            acc = cadd(acc, cmul(K, dens[j]));
+        }
+        phi[a] = acc;
+    }
+    __syncthreads();
+    const int64_t so = slot[task];
+    for (int r = tid; r < s; r += LEAF_BLOCK) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int a = 0; a < ny; ++a) acc = cadd(acc, cmul(W[r + (int64_t)a * s], phi[a]));
+        od[so + r] = cadd(od[so + r], acc);
+    }
+}
+
+// L2T: incoming equivalent densities q = W^T y, then E_dn q at the targets.
+__global__ __launch_bounds__(LEAF_BLOCK) void k_l2t(const int64_t *__restrict__ start, const int64_t *__restrict__ end,
+                                                    const int64_t *__restrict__ slot, const int *__restrict__ tmpl,
+                                                    const double *__restrict__ center, const int *__restrict__ t_s,
+                                                    const int *__restrict__ t_ny, const int64_t *__restrict__ t_yoff,
+                                                    const int64_t *__restrict__ t_woff, const double *__restrict__ tY,
+                                                    const double2 *__restrict__ tW, const double *__restrict__ X,
+                                                    const double *__restrict__ Y, const double *__restrict__ Z,
+                                                    const double *__restrict__ NX, const double *__restrict__ NY,
+                                                    const double *__restrict__ NZ, const double2 *__restrict__ id,
+                                                    double2 *__restrict__ res, double k, OpC c)
+{
+    extern __shared__ double2 q[];
+    const int task = blockIdx.x, tid = threadIdx.x;
+    const int lev = tmpl[task];
+    const int s = t_s[lev], ny = t_ny[lev];
+    const double *Yt = tY + t_yoff[lev];
+    const double2 *W = tW + t_woff[lev];
+    const double cx = center[3 * task], cy = center[3 * task + 1], cz = center[3 * task + 2];
+    const int64_t so = slot[task];
+    for (int a = tid; a < ny; a += LEAF_BLOCK) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int r = 0; r < s; ++r) acc = cadd(acc, cmul(W[r + (int64_t)a * s], id[so + r]));
+        q[a] = acc;
+    }
+    __syncthreads();
+    const int64_t i0 = start[task], i1 = end[task];
+    for (int64_t i = i0 + tid; i < i1; i += LEAF_BLOCK) {
+        const double xi = X[i], yi = Y[i], zi = Z[i], nxi = NX[i], nyi = NY[i], nzi = NZ[i];
+        double2 acc = make_double2(0.0, 0.0);
+        for (int a = 0; a < ny; ++a) {
+            const double2 K =
+                kernel_tgt(xi - (cx + Yt[3 * a]), yi - (cy + Yt[3 * a + 1]), zi - (cz + Yt[3 * a + 2]), nxi, nyi, nzi, k, c);
+            acc = cadd(acc, cmul(K, q[a]));
+        }
+        res[i] = cadd(res[i], acc);
+    }
+}
+
+// Batched segmented GEMV: out[o] += sum_e op(M_e) in[e]; one block per output slot.
+constexpr int GEMV_BLOCK = 128;
+constexpr int GEMV_MAXROWS = 2 * GEMV_BLOCK;
+__global__ __launch_bounds__(GEMV_BLOCK) void k_gemv(const int64_t *__restrict__ out_off, const int *__restrict__ ptr,
+                                                     const int64_t *__restrict__ in_off,
+                                                     const int64_t *__restrict__ mat_off, const int *__restrict__ rank,
+                                                     int rows, int cols, int trans, const double2 *__restrict__ mat,
+                                                     const double2 *__restrict__ in, double2 *__restrict__ out)
+{
+    extern __shared__ double2 sh[];
+    double2 *xs = sh;          // cols
+    double2 *ts = sh + cols;   // low-rank intermediate
+    const int o = blockIdx.x, tid = threadIdx.x;
+    double2 acc0 = make_double2(0.0, 0.0), acc1 = make_double2(0.0, 0.0);
+    const int i0 = tid, i1 = tid + GEMV_BLOCK;
+    for (int e = ptr[o]; e < ptr[o + 1]; ++e) {
+        __syncthreads();
+        const double2 *x = in + in_off[e];
+        for (int j = tid; j < cols; j += GEMV_BLOCK) xs[j] = x[j];
+        __syncthreads();
+        const double2 *M = mat + mat_off[e];
+        const int r = rank[e];
+        if (r < 0) {
+            if (!trans) {
+                if (i0 < rows)
+                    for (int j = 0; j < cols; ++j) acc0 = cadd(acc0, cmul(M[i0 + (int64_t)j * rows], xs[j]));
+                if (i1 < rows)
+                    for (int j = 0; j < cols; ++j) acc1 = cadd(acc1, cmul(M[i1 + (int64_t)j * rows], xs[j]));
+            } else {
+                // M is cols x rows (column-major); use its transpose
+                if (i0 < rows)
+                    for (int j = 0; j < cols; ++j) acc0 = cadd(acc0, cmul(M[j + (int64_t)i0 * cols], xs[j]));
+                if (i1 < rows)
+                    for (int j = 0; j < cols; ++j) acc1 = cadd(acc1, cmul(M[j + (int64_t)i1 * cols], xs[j]));
+            }
+        } else {
+            const double2 *U = M;
+            const double2 *V = M + (int64_t)rows * r;
+            for (int qq = tid; qq < r; qq += GEMV_BLOCK) {
+                double2 t = make_double2(0.0, 0.0);
+                for (int j = 0; j < cols; ++j) t = cadd(t, cmul(V[qq + (int64_t)j * r], xs[j]));
+                ts[qq] = t;
+            }
+            __syncthreads();
+            if (i0 < rows)
+                for (int qq = 0; qq < r; ++qq) acc0 = cadd(acc0, cmul(U[i0 + (int64_t)qq * rows], ts[qq]));
+            if (i1 < rows)
+                for (int qq = 0; qq < r; ++qq) acc1 = cadd(acc1, cmul(U[i1 + (int64_t)qq * rows], ts[qq]));
+        }
+    }
+    const int64_t ob = out_off[o];
+    if (i0 < rows) out[ob + i0] = cadd(out[ob + i0], acc0);
+    if (i1 < rows) out[ob + i1] = cadd(out[ob + i1], acc1);
+}
+
+// Near-field correction, caller order: out_i += sum_c val_c in_{col_c}.
+__global__ void k_corr(const int64_t *__restrict__ rp, const int64_t *__restrict__ col,
+                       const double2 *__restrict__ val, const double2 *__restrict__ in, double2 *__restrict__ out,
+                       int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t c = rp[i]; c < rp[i + 1]; ++c) acc = cadd(acc, cmul(val[c], in[col[c]]));
+    out[i] = cadd(out[i], acc);
+}
+
+__global__ void k_plane_wave(const double *__restrict__ X, const double *__restrict__ Y, const double *__restrict__ Z,
+                             const double *__restrict__ NX, const double *__restrict__ NY, const double *__restrict__ NZ,
+                             const int64_t *__restrict__ perm, double k, double d0, double d1, double d2,
+                             double2 *__restrict__ rhs, int64_t n)
+{
+    // b = u_inc + alpha du_inc/dn_x, u_inc = exp(ik x.d), du_inc/dn = ik (d.n) u_inc, alpha = i/k
+    // => b = u_inc (1 + (i/k)(ik)(d.n)) = u_inc (1 - d.n)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double sn, cs;
+    sincos(k * (X[i] * d0 + Y[i] * d1 + Z[i] * d2), &sn, &cs);
+    const double f = 1.0 - (NX[i] * d0 + NY[i] * d1 + NZ[i] * d2);
+    rhs[perm[i]] = make_double2(cs * f, sn * f);
+}
+
+// ---------------------------------------------------------------- host side
+template <typename T>
+static T *dalloc(Device &D, size_t n)
+{
+    if (n == 0) n = 1;
+    void *p = nullptr;
+    HIP_CHECK(hipMalloc(&p, n * sizeof(T)));
+    D.allocs.push_back(p);
+    D.bytes += n * sizeof(T);
+    return (T *)p;
+}
+
+template <typename T>
+static T *dupload(Device &D, const std::vector<T> &v)
+{
+    T *p = dalloc<T>(D, v.size());
+    if (!v.empty()) HIP_CHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+}
+
+static DGemv upload_gemv(Device &D, const GemvList &G)
+{
+    DGemv g;
+    g.n_out = (int)G.out_off.size();
+    g.rows = G.rows;
+    g.cols = G.cols;
+    g.trans = G.trans;
+    g.n_ent = (int64_t)G.in_off.size();
+    if (g.n_out == 0) return g;
+    g.out_off = dupload(D, G.out_off);
+    g.ptr = dupload(D, G.ptr);
+    g.in_off = dupload(D, G.in_off);
+    g.mat_off = dupload(D, G.mat_off);
+    g.rank = dupload(D, G.rank);
+    for (int r : G.rank) g.max_rank = std::max(g.max_rank, r);
+    if (g.rows > GEMV_MAXROWS) throw std::runtime_error("reduced dimension exceeds the GEMV kernel's limit");
+    return g;
+}
+
+static DLeaf upload_leaf(Device &D, const Plan &P, const std::vector<LeafTask> &T)
+{
+    DLeaf L;
+    L.n = (int)T.size();
+    if (L.n == 0) return L;
+    std::vector<int64_t> s(L.n), e(L.n), sl(L.n);
+    std::vector<int> tm(L.n);
+    std::vector<double> c(3 * L.n);
+    for (int i = 0; i < L.n; ++i) {
+        s[i] = T[i].start;
+        e[i] = T[i].end;
+        sl[i] = T[i].slot_off;
+        tm[i] = T[i].tmpl;
+        c[3 * i] = T[i].center[0];
+        c[3 * i + 1] = T[i].center[1];
+        c[3 * i + 2] = T[i].center[2];
+    }
+    L.start = dupload(D, s);
+    L.end = dupload(D, e);
+    L.slot = dupload(D, sl);
+    L.tmpl = dupload(D, tm);
+    L.center = dupload(D, c);
+    return L;
+}
+
+void device_upload(Plan &P)
+{
+    Device *Dp = new Device();
+    P.dev = Dp;
+    Device &D = *Dp;
+    HIP_CHECK(hipGetDevice(&D.device));
+    D.x = dupload(D, P.px);
+    D.y = dupload(D, P.py);
+    D.z = dupload(D, P.pz);
+    D.nx = dupload(D, P.pnx);
+    D.ny = dupload(D, P.pny);
+    D.nz = dupload(D, P.pnz);
+    D.w = dupload(D, P.pw);
+    D.perm = dupload(D, P.perm);
+    D.n_leaf = (int)P.leaves.size();
+    D.p2p_ts = dupload(D, P.p2p_tgt_start);
+    D.p2p_te = dupload(D, P.p2p_tgt_end);
+    D.p2p_ptr = dupload(D, P.p2p_ptr);
+    D.p2p_ss = dupload(D, P.p2p_src_start);
+    D.p2p_se = dupload(D, P.p2p_src_end);
+    // templates
+    const int nlev = (int)P.levels.size();
+    D.n_lev = nlev;
+    if (P.opt.far_field) {
+        std::vector<int> ts(nlev, 0), tny(nlev, 0);
+        std::vector<int64_t> yoff(nlev, 0), woff(nlev, 0);
+        std::vector<double> Yall;
+        std::vector<double2> Wall;
+        for (int l = 0; l < nlev; ++l) {
+            const LevelTemplate &T = P.tmpl[l];
+            ts[l] = T.s;
+            tny[l] = (int)T.Y.size() / 3;
+            yoff[l] = (int64_t)Yall.size();
+            woff[l] = (int64_t)Wall.size();
+            Yall.insert(Yall.end(), T.Y.begin(), T.Y.end());
+            for (const cplx &v : T.W.a) Wall.push_back(make_double2(v.real(), v.imag()));
+        }
+        D.t_s = dupload(D, ts);
+        D.t_ny = dupload(D, tny);
+        D.t_yoff = dupload(D, yoff);
+        D.t_woff = dupload(D, woff);
+        D.t_Y = dupload(D, Yall);
+        D.t_W = dupload(D, Wall);
+        std::vector<double2> mp(P.matpool.size());
+        for (size_t i = 0; i < mp.size(); ++i) mp[i] = make_double2(P.matpool[i].real(), P.matpool[i].imag());
+        D.mat = dupload(D, mp);
+        D.m2m.resize(nlev);
+        D.m2l.resize(nlev);
+        D.l2l.resize(nlev);
+        for (int l = 0; l < nlev; ++l) {
+            D.m2m[l] = upload_gemv(D, P.m2m_lists[l]);
+            D.m2l[l] = upload_gemv(D, P.m2l_lists[l]);
+            D.l2l[l] = upload_gemv(D, P.l2l_lists[l]);
+        }
+        D.s2m = upload_leaf(D, P, P.s2m_tasks);
+        D.l2t = upload_leaf(D, P, P.l2t_tasks);
+        D.n_od = P.out_total;
+        D.n_id = P.in_total;
+        D.od = dalloc<double2>(D, D.n_od);
+        D.id = dalloc<double2>(D, D.n_id);
+    }
+    D.dens = dalloc<double2>(D, P.N);
+    D.res = dalloc<double2>(D, P.N);
+    if (P.has_corr) {
+        D.corr_nnz = (int64_t)P.corr_col.size();
+        D.corr_ptr = dupload(D, P.corr_ptr);
+        D.corr_col = dupload(D, P.corr_col);
+        std::vector<double2> cv(P.corr_val.size());
+        for (size_t i = 0; i < cv.size(); ++i) cv[i] = make_double2(P.corr_val[i].real(), P.corr_val[i].imag());
+        D.corr_val = dupload(D, cv);
+    }
+    for (auto &e : D.ev) HIP_CHECK(hipEventCreate(&e));
+}
+
+void device_free(Plan &P)
+{
+    if (!P.dev) return;
+    Device &D = *P.dev;
+    for (void *p : D.allocs) (void)hipFree(p);
+    for (void *p : {(void *)D.gm_V, (void *)D.gm_w, (void *)D.gm_r, (void *)D.gm_h, (void *)D.gm_red_c})
+        if (p) (void)hipFree(p);
+    for (auto &e : D.ev)
+        if (e) (void)hipEventDestroy(e);
+    delete P.dev;
+    P.dev = nullptr;
+}
+
+static OpC op_coef(int op, double k)
+{
+    const double2 z = make_double2(0, 0), one = make_double2(1, 0), al = make_double2(0, 1.0 / k);
+    OpC c;
+    switch (op) {
+    case 0:  // RAW_H
+    case 3:  // BM_H
+        c.c0 = z; c.c1 = one; c.d0 = one; c.d1 = al; break;
+    case 1:  // RAW_G
+    case 4:  // BM_G
+        c.c0 = one; c.c1 = z; c.d0 = one; c.d1 = al; break;
+    default:  // RAW_T1
+        c.c0 = one; c.c1 = al; c.d0 = one; c.d1 = z; break;
+    }
+    auto mul = [](double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); };
+    c.cd00 = mul(c.c0, c.d0);
+    c.cd10 = mul(c.c1, c.d0);
+    c.cd01 = mul(c.c0, c.d1);
+    c.cd11 = mul(c.c1, c.d1);
+    return c;
+}
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+static void run_gemv(const DGemv &g, const double2 *mat, const double2 *in, double2 *out, hipStream_t st)
+{
+    if (g.n_out == 0) return;
+    const size_t shm = sizeof(double2) * (g.cols + std::max(g.max_rank, 1));
+    hipLaunchKernelGGL(k_gemv, dim3(g.n_out), dim3(GEMV_BLOCK), shm, st, g.out_off, g.ptr, g.in_off, g.mat_off, g.rank,
+                       g.rows, g.cols, g.trans, mat, in, out);
+}
+
+void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st)
+{
+    Device &D = *P.dev;
+    const int64_t N = P.N;
+    const OpC c = op_coef(op, P.k);
+    const bool bm = (op == 3 || op == 4);
+    const bool tm = D.timing != 0;
+    if (tm) HIP_CHECK(hipEventRecord(D.ev[0], st));
+    hipLaunchKernelGGL(k_permute_in, dim3(nblk(N, 256)), dim3(256), 0, st, in, D.perm, D.w, D.dens, N);
+    if (tm) HIP_CHECK(hipEventRecord(D.ev[1], st));
+    hipLaunchKernelGGL(k_p2p, dim3(D.n_leaf), dim3(P2P_TILE), 0, st, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
+                       D.x, D.y, D.z, D.nx, D.ny, D.nz, D.dens, D.res, P.k, c);
+    if (tm) HIP_CHECK(hipEventRecord(D.ev[2], st));
+    if (P.opt.far_field) {
+        if (D.n_od) hipLaunchKernelGGL(k_fill_zero, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, D.od, D.n_od);
+        if (D.n_id) hipLaunchKernelGGL(k_fill_zero, dim3(nblk(D.n_id, 256)), dim3(256), 0, st, D.id, D.n_id);
+        const size_t shm_leaf = sizeof(double2) * std::max(P.max_Y_leaf, 1);
+        if (D.s2m.n)
+            hipLaunchKernelGGL(k_s2m, dim3(D.s2m.n), dim3(LEAF_BLOCK), shm_leaf, st, D.s2m.start, D.s2m.end,
+                               D.s2m.slot, D.s2m.tmpl, D.s2m.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, D.t_W,
+                               D.x, D.y, D.z, D.nx, D.ny, D.nz, D.dens, D.od, P.k, c);
+        if (tm) HIP_CHECK(hipEventRecord(D.ev[3], st));
+        for (int l = D.n_lev - 2; l >= 0; --l) run_gemv(D.m2m[l], D.mat, D.od, D.od, st);
+        if (tm) HIP_CHECK(hipEventRecord(D.ev[4], st));
+        for (int l = 0; l < D.n_lev; ++l) run_gemv(D.m2l[l], D.mat, D.od, D.id, st);
+        if (tm) HIP_CHECK(hipEventRecord(D.ev[5], st));
+        for (int l = 1; l < D.n_lev; ++l) run_gemv(D.l2l[l], D.mat, D.id, D.id, st);
+        if (tm) HIP_CHECK(hipEventRecord(D.ev[6], st));
+        if (D.l2t.n)
+            hipLaunchKernelGGL(k_l2t, dim3(D.l2t.n), dim3(LEAF_BLOCK), shm_leaf, st, D.l2t.start, D.l2t.end,
+                               D.l2t.slot, D.l2t.tmpl, D.l2t.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, D.t_W,
+                               D.x, D.y, D.z, D.nx, D.ny, D.nz, D.id, D.res, P.k, c);
+    } else if (tm) {
+        for (int e = 3; e <= 6; ++e) HIP_CHECK(hipEventRecord(D.ev[e], st));
+    }
+    if (tm) HIP_CHECK(hipEventRecord(D.ev[7], st));
+    hipLaunchKernelGGL(k_permute_out, dim3(nblk(N, 256)), dim3(256), 0, st, D.res, D.perm, in, bm ? 0.5 : 0.0, out, N);
+    if (tm) HIP_CHECK(hipEventRecord(D.ev[8], st));
+    if (bm && D.corr_nnz)
+        hipLaunchKernelGGL(k_corr, dim3(nblk(N, 256)), dim3(256), 0, st, D.corr_ptr, D.corr_col, D.corr_val, in, out, N);
+    if (tm) {
+        HIP_CHECK(hipEventRecord(D.ev[9], st));
+        HIP_CHECK(hipEventSynchronize(D.ev[9]));
+        float ms;
+        // P2P, S2M, M2M, M2L, L2L, L2T, correction, permutations
+        const int a[8] = {1, 2, 3, 4, 5, 6, 8, 0}, b[8] = {2, 3, 4, 5, 6, 7, 9, 1};
+        for (int t = 0; t < 7; ++t) {
+            HIP_CHECK(hipEventElapsedTime(&ms, D.ev[a[t]], D.ev[b[t]]));
+            D.phase_ms[t] = ms;
+        }
+        float m0, m1;
+        HIP_CHECK(hipEventElapsedTime(&m0, D.ev[0], D.ev[1]));
+        HIP_CHECK(hipEventElapsedTime(&m1, D.ev[7], D.ev[8]));
+        D.phase_ms[7] = m0 + m1;
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t st)
+{
+    Device &D = *P.dev;
+    hipLaunchKernelGGL(k_plane_wave, dim3(nblk(P.N, 256)), dim3(256), 0, st, D.x, D.y, D.z, D.nx, D.ny, D.nz, D.perm,
+                       P.k, d[0], d[1], d[2], rhs, P.N);
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace fdbem

@@ -1,0 +1,74 @@
+// Device-resident plan data and the mat-vec / solver launch sequences.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.hpp"
+
+namespace fdbem {
+
+struct DGemv {
+    int n_out = 0, rows = 0, cols = 0, trans = 0, max_rank = 0;
+    int64_t n_ent = 0;
+    int64_t *out_off = nullptr;
+    int *ptr = nullptr;
+    int64_t *in_off = nullptr;
+    int64_t *mat_off = nullptr;
+    int *rank = nullptr;
+};
+
+struct DLeaf {
+    int n = 0;
+    int64_t *start = nullptr, *end = nullptr, *slot = nullptr;
+    int *tmpl = nullptr;
+    double *center = nullptr;  // n x 3
+};
+
+struct Device {
+    int device = 0;
+    // points (sorted order)
+    double *x = nullptr, *y = nullptr, *z = nullptr, *nx = nullptr, *ny = nullptr, *nz = nullptr, *w = nullptr;
+    int64_t *perm = nullptr;
+    // near field
+    int n_leaf = 0;
+    int64_t *p2p_ts = nullptr, *p2p_te = nullptr, *p2p_ss = nullptr, *p2p_se = nullptr;
+    int *p2p_ptr = nullptr;
+    // templates
+    int n_lev = 0;
+    int *t_s = nullptr, *t_ny = nullptr;
+    int64_t *t_yoff = nullptr, *t_woff = nullptr;
+    double *t_Y = nullptr;       // concatenated check points
+    double2 *t_W = nullptr;      // concatenated W matrices
+    // translations
+    double2 *mat = nullptr;
+    std::vector<DGemv> m2m, m2l, l2l;  // per level
+    DLeaf s2m, l2t;
+    // work vectors
+    double2 *dens = nullptr;     // weighted sorted density (N)
+    double2 *res = nullptr;      // sorted result (N)
+    double2 *od = nullptr, *id = nullptr;
+    int64_t n_od = 0, n_id = 0;
+    // near-field correction (caller order, CSR)
+    int64_t corr_nnz = 0;
+    int64_t *corr_ptr = nullptr, *corr_col = nullptr;
+    double2 *corr_val = nullptr;
+    // GMRES work space (allocated on first solve)
+    int gm_m = 0;
+    double2 *gm_V = nullptr, *gm_w = nullptr, *gm_x = nullptr, *gm_r = nullptr, *gm_h = nullptr;
+    double2 *gm_red_c = nullptr;
+    // timing
+    int timing = 0;
+    hipEvent_t ev[10] = {};
+    double phase_ms[8] = {0};
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+};
+
+void device_upload(Plan &P);
+void device_free(Plan &P);
+void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st);
+void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t st);
+int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int restart, int precond, double2 *x,
+                 int *iters, double *relres, double *hist, hipStream_t st);
+
+}  // namespace fdbem

@@ -1,0 +1,106 @@
+// Host-side plan construction: copies the caller's geometry, sorts it into
+// octree order and runs the FP64 set-up stages.
+#include <chrono>
+#include <cmath>
+#include <sstream>
+#include <stdexcept>
+
+#include "plan.hpp"
+
+namespace fdbem {
+
+static double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+Plan *plan_create_host(int64_t n, const double *pts, const double *nrm, const double *w, int64_t n_elem,
+                       const double *elem, double k, double eps, const Options &opt)
+{
+    if (n <= 0 || !pts || !nrm || !w) throw std::invalid_argument("empty geometry");
+    if (!(k > 0) || !std::isfinite(k)) throw std::invalid_argument("wavenumber must be positive");
+    if (!(eps > 0 && eps < 1)) throw std::invalid_argument("eps must lie in (0,1)");
+    if (n_elem > 0 && (n_elem * 6 != n || !elem)) throw std::invalid_argument("elements must carry 6 nodes each");
+    if (opt.leaf_cap < 1) throw std::invalid_argument("leaf_cap must be >= 1");
+    Plan *P = new Plan();
+    try {
+        P->N = n;
+        P->k = k;
+        P->eps = eps;
+        P->lambda = 2.0 * M_PI / k;
+        P->opt = opt;
+        P->px.resize(n);
+        P->py.resize(n);
+        P->pz.resize(n);
+        P->pnx.resize(n);
+        P->pny.resize(n);
+        P->pnz.resize(n);
+        P->pw.resize(n);
+        for (int64_t i = 0; i < n; ++i) {
+            P->px[i] = pts[3 * i];
+            P->py[i] = pts[3 * i + 1];
+            P->pz[i] = pts[3 * i + 2];
+            P->pnx[i] = nrm[3 * i];
+            P->pny[i] = nrm[3 * i + 1];
+            P->pnz[i] = nrm[3 * i + 2];
+            P->pw[i] = w[i];
+            if (!std::isfinite(P->px[i] + P->py[i] + P->pz[i] + P->pw[i]))
+                throw std::invalid_argument("non-finite geometry");
+        }
+        if (n_elem > 0) {
+            P->n_elem = n_elem;
+            P->elem.assign(elem, elem + 18 * n_elem);
+        }
+        double t0 = now_s();
+        build_tree(*P);
+        build_lists(*P);
+        double t1 = now_s();
+        P->t_setup_tree = t1 - t0;
+        if (P->opt.far_field) {
+            build_templates(*P);
+            double t2 = now_s();
+            P->t_setup_tmpl = t2 - t1;
+            build_operators(*P);
+            P->t_setup_ops = now_s() - t2;
+        }
+        if (n_elem > 0 && P->opt.corrections) {
+            double t3 = now_s();
+            build_corrections(*P);
+            P->t_setup_corr = now_s() - t3;
+        }
+    } catch (...) {
+        delete P;
+        throw;
+    }
+    return P;
+}
+
+std::string plan_stats(const Plan &P)
+{
+    std::ostringstream o;
+    o.precision(6);
+    o << "{\"N\": " << P.N << ", \"k\": " << P.k << ", \"eps\": " << P.eps << ", \"lambda\": " << P.lambda
+      << ", \"root_w\": " << P.root_w << ", \"n_levels\": " << P.levels.size() << ", \"n_leaves\": " << P.leaves.size()
+      << ", \"p2p_pairs\": " << P.p2p_pairs << ", \"matpool_bytes\": " << P.matpool.size() * 16
+      << ", \"density_slots_out\": " << P.out_total << ", \"density_slots_in\": " << P.in_total
+      << ", \"corr_nnz\": " << P.corr_col.size() << ", \"setup_s\": {\"tree\": " << P.t_setup_tree
+      << ", \"templates\": " << P.t_setup_tmpl << ", \"operators\": " << P.t_setup_ops
+      << ", \"corrections\": " << P.t_setup_corr << "}, \"levels\": [";
+    for (size_t l = 0; l < P.levels.size(); ++l) {
+        const LevelInfo &L = P.levels[l];
+        int64_t npairs = l < P.m2l.size() ? (int64_t)P.m2l[l].size() : 0;
+        int nlr = 0, nk = l < P.m2l_nkeys.size() ? P.m2l_nkeys[l] : 0;
+        if (l < P.m2l_lists.size())
+            for (size_t q = 0; q < P.m2l_lists[l].rank.size(); ++q) nlr += P.m2l_lists[l].rank[q] >= 0;
+        o << (l ? ", " : "") << "{\"w\": " << L.w << ", \"hf\": " << (L.hf ? 1 : 0) << ", \"m\": " << L.m
+          << ", \"cubes\": " << L.cubes.size() << ", \"out_slots\": " << L.n_out << ", \"in_slots\": " << L.n_in
+          << ", \"s\": " << (l < P.tmpl.size() ? P.tmpl[l].s : 0)
+          << ", \"n_equiv\": " << (l < P.tmpl.size() ? P.tmpl[l].X.size() / 3 : 0)
+          << ", \"n_check\": " << (l < P.tmpl.size() ? P.tmpl[l].Y.size() / 3 : 0) << ", \"m2l_pairs\": " << npairs
+          << ", \"m2l_ops\": " << nk << ", \"m2l_pairs_lowrank\": " << nlr << "}";
+    }
+    o << "]}";
+    return o.str();
+}
+
+}  // namespace fdbem

@@ -1,0 +1,453 @@
+// Equivalent/check point templates, pseudo-inverses and the compressed
+// translation operators of the fast directional algorithm.
+//
+// * Low frequency (w < lambda): kernel-independent surface grids as in the
+//   kernel-independent FMM: equivalent points on a cube surface of half-width
+//   1.05 w/2, check points on one of half-width 2.95 w/2 (section 3.1.2).
+// * High frequency (w = m lambda): one template for direction +x, rotated to
+//   each wedge; the pseudo-inverse is shared by all wedges (section 3.1.2).
+//   Check points fill the cone of the wedge (cell of the face grid plus the
+//   angular radius of a target cube at the smallest interaction distance)
+//   between that distance and the far field; equivalent points are a skeleton
+//   of the cube's ball selected by a randomised pivoted Gram-Schmidt on the
+//   check-to-candidate interaction matrix.
+// * R = G(check, equivalent) = U S V^H, truncated at sigma_i >= eps sigma_1
+//   (eqs. eq_svdr, eq_invr).  Compressed operators (eqs. eq_cmps .. eq_cmpt):
+//     S2M:  S~ = S~^-1 U~^H E_up           (applied on the fly from W = S~^-1 U~^H)
+//     M2M:  M~ = W_parent E(parent check, child equivalent) V~_child
+//     M2L:  K~ = V~^T G(target equivalent, source equivalent) V~
+//           (incoming check points are the outgoing equivalent points, so
+//            U~_dn^H = V~^T, section 3.2 transpose identities)
+//     L2L:  L~ = M~^T
+//     L2T:  T~ = E_dn conj(U~) S~^-1 = E_dn W^T
+// * Low-rank M2L (eq. eq_lrdk): K~ ~= U^ V^ with V^ = S^ Q^^H, truncating
+//   sigma < eps sigma_1; used iff its rank r < s/2, else K~ is applied.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <stdexcept>
+
+#include "plan.hpp"
+
+namespace fdbem {
+
+namespace {
+
+double svd_eps(const Plan &P) { return P.opt.svd_eps > 0 ? P.opt.svd_eps : P.eps; }
+double lr_eps(const Plan &P) { return P.opt.lowrank_eps > 0 ? P.opt.lowrank_eps : P.eps; }
+
+std::vector<double> cube_surface(int p, double a)
+{
+    std::vector<double> pts;
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j)
+            for (int l = 0; l < p; ++l) {
+                if (i != 0 && i != p - 1 && j != 0 && j != p - 1 && l != 0 && l != p - 1) continue;
+                pts.push_back(-a + 2.0 * a * i / (p - 1));
+                pts.push_back(-a + 2.0 * a * j / (p - 1));
+                pts.push_back(-a + 2.0 * a * l / (p - 1));
+            }
+    return pts;
+}
+
+// quasi-uniform points on the cap {theta <= th} around +x (Fibonacci lattice)
+void cap_points(int n, double th, double radius, std::vector<double> &out)
+{
+    const double ga = M_PI * (3.0 - std::sqrt(5.0));
+    const double cmin = std::cos(th);
+    for (int i = 0; i < n; ++i) {
+        const double c = 1.0 - (1.0 - cmin) * (i + 0.5) / n;
+        const double s = std::sqrt(std::max(0.0, 1.0 - c * c));
+        const double ph = ga * i;
+        out.push_back(radius * c);
+        out.push_back(radius * s * std::cos(ph));
+        out.push_back(radius * s * std::sin(ph));
+    }
+}
+
+void finish_template(LevelTemplate &T, double k, double eps)
+{
+    const int ny = (int)T.Y.size() / 3, nx = (int)T.X.size() / 3;
+    CMat R(ny, nx);
+    for (int j = 0; j < nx; ++j)
+        for (int i = 0; i < ny; ++i) R(i, j) = kernel_G(&T.Y[3 * i], &T.X[3 * j], k);
+    SVD d = svd(R);
+    const int s = std::max(1, truncation_rank(d.s, eps));
+    T.s = s;
+    T.sing = d.s;
+    T.Vt = CMat(nx, s);
+    T.W = CMat(s, ny);
+    for (int c = 0; c < s; ++c) {
+        for (int i = 0; i < nx; ++i) T.Vt(i, c) = d.V(i, c);
+        for (int i = 0; i < ny; ++i) T.W(c, i) = std::conj(d.U(i, c)) / d.s[c];
+    }
+}
+
+LevelTemplate lf_template(const Plan &P, double w)
+{
+    LevelTemplate T;
+    T.hf = false;
+    T.w = w;
+    int p = P.opt.lf_grid;
+    if (p <= 0) p = std::max(4, (int)std::ceil(-std::log10(svd_eps(P))) + 4);
+    T.X = cube_surface(p, 1.05 * 0.5 * w);
+    T.Y = cube_surface(p, 2.95 * 0.5 * w);
+    finish_template(T, P.k, svd_eps(P));
+    return T;
+}
+
+double cell_angle(int m)
+{
+    // largest angle between a face cell's central direction and its corners
+    double worst = 0;
+    for (int iu = 0; iu < m; ++iu)
+        for (int it = 0; it < m; ++it) {
+            const double cu = (2.0 * iu + 1.0 - m) / m, ct = (2.0 * it + 1.0 - m) / m;
+            const double c[3] = {1.0, cu, ct};
+            const double cn = std::sqrt(1 + cu * cu + ct * ct);
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    const double u = (2.0 * (iu + a) - m) / m, t = (2.0 * (it + b) - m) / m;
+                    const double q[3] = {1.0, u, t};
+                    const double qn = std::sqrt(1 + u * u + t * t);
+                    const double d = (c[0] * q[0] + c[1] * q[1] + c[2] * q[2]) / (cn * qn);
+                    worst = std::max(worst, std::acos(std::min(1.0, d)));
+                }
+        }
+    return worst;
+}
+
+LevelTemplate hf_template(const Plan &P, const LevelInfo &L)
+{
+    LevelTemplate T;
+    T.hf = true;
+    T.w = L.w;
+    T.m = L.m;
+    const double w = L.w, lam = P.lambda, k = P.k;
+    const double rho = 1.05 * 0.5 * std::sqrt(3.0) * w;
+    const int reach = (int)std::floor(P.opt.c_d * k * w + 1e-9) + 1;  // near if Chebyshev offset <= reach
+    const double rc_min = (reach + 1) * w;                            // smallest interacting centre distance
+    const double margin = std::asin(std::min(1.0, rho / rc_min));
+    const double th = std::min(M_PI / 2, cell_angle(L.m) + 1.25 * margin + 0.02);
+    const double r_in = rc_min - rho;
+    const double r_out = std::max(16.0 * r_in, 4.0 * P.root_w);
+    T.theta_cone = th;
+    T.r_in = r_in;
+    T.r_out = r_out;
+    // check candidates: caps at log-spaced radii
+    const double dth = lam / (6.0 * rho);
+    const int ndir = std::min(4000, std::max(24, (int)std::ceil(2.0 * M_PI * (1.0 - std::cos(th)) / (dth * dth))));
+    const int nr = 10;
+    std::vector<double> Y;
+    for (int q = 0; q < nr; ++q) {
+        const double r = r_in * std::pow(r_out / r_in, (double)q / (nr - 1));
+        cap_points(q == 0 ? 2 * ndir : ndir, th, r, Y);
+    }
+    // equivalent candidates: sphere of radius rho and two inner shells
+    std::vector<double> Xc;
+    const double shells[3] = {1.0, 0.7, 0.4};
+    for (double f : shells) {
+        const double rr = rho * f;
+        const int n = std::max(16, (int)std::ceil(4.0 * M_PI * rr * rr / std::pow(lam / 5.0, 2)));
+        cap_points(n, M_PI, rr, Xc);
+    }
+    const int ny = (int)Y.size() / 3, nxc = (int)Xc.size() / 3;
+    // randomised column skeleton of A = G(Y, Xc): sketch B = Omega A
+    const int ell = std::min(ny, 320);
+    CMat Om = gaussian_sketch(ell, ny, 12345 + L.m);
+    CMat Bsk(ell, nxc);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int j = 0; j < nxc; ++j) {
+        std::vector<cplx> col(ny);
+        for (int i = 0; i < ny; ++i) col[i] = kernel_G(&Y[3 * i], &Xc[3 * j], k);
+        for (int a = 0; a < ell; ++a) {
+            cplx s = 0.0;
+            for (int i = 0; i < ny; ++i) s += Om(a, i) * col[i];
+            Bsk(a, j) = s;
+        }
+    }
+    const double id_tol = 0.05 * svd_eps(P);
+    std::vector<int> sel = select_columns(Bsk, id_tol, ell - 8);
+    T.X.resize(3 * sel.size());
+    for (size_t t = 0; t < sel.size(); ++t)
+        for (int d = 0; d < 3; ++d) T.X[3 * t + d] = Xc[3 * sel[t] + d];
+    T.Y = Y;
+    finish_template(T, k, svd_eps(P));
+    return T;
+}
+
+void rotate(const std::array<double, 9> &R, const std::vector<double> &in, std::vector<double> &out)
+{
+    const size_t n = in.size() / 3;
+    out.resize(in.size());
+    for (size_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a)
+            out[3 * i + a] = R[3 * a] * in[3 * i] + R[3 * a + 1] * in[3 * i + 1] + R[3 * a + 2] * in[3 * i + 2];
+}
+
+int64_t push_matrix(Plan &P, const CMat &A)
+{
+    const int64_t off = (int64_t)P.matpool.size();
+    P.matpool.insert(P.matpool.end(), A.a.begin(), A.a.end());
+    return off;
+}
+
+}  // namespace
+
+void build_templates(Plan &P)
+{
+    const int nlev = (int)P.levels.size();
+    P.tmpl.assign(nlev, LevelTemplate());
+    std::vector<int> needed;
+    for (int l = 0; l < nlev; ++l) {
+        const LevelInfo &L = P.levels[l];
+        if (L.n_out + L.n_in > 0) needed.push_back(l);
+    }
+    for (int l : needed) {
+        const LevelInfo &L = P.levels[l];
+        P.tmpl[l] = L.hf ? hf_template(P, L) : lf_template(P, L.w);
+    }
+    P.max_s = 0;
+    P.max_Y = 0;
+    for (int l : needed) {
+        P.max_s = std::max(P.max_s, P.tmpl[l].s);
+        P.max_Y = std::max(P.max_Y, (int)P.tmpl[l].Y.size() / 3);
+    }
+}
+
+void build_operators(Plan &P)
+{
+    const int nlev = (int)P.levels.size();
+    P.matpool.clear();
+    // density layout
+    int64_t ob = 0, ib = 0;
+    for (int l = 0; l < nlev; ++l) {
+        LevelInfo &L = P.levels[l];
+        L.out_base = ob;
+        L.in_base = ib;
+        ob += (int64_t)L.n_out * P.tmpl[l].s;
+        ib += (int64_t)L.n_in * P.tmpl[l].s;
+    }
+    P.out_total = ob;
+    P.in_total = ib;
+
+    // ---- M2L operators per level
+    P.m2l_lists.assign(nlev, GemvList());
+    for (int l = 0; l < nlev; ++l) {
+        const LevelInfo &L = P.levels[l];
+        const int nk = P.m2l_nkeys[l];
+        if (nk == 0) continue;
+        const LevelTemplate &T = P.tmpl[l];
+        const int s = T.s, nx = (int)T.X.size() / 3;
+        std::vector<CMat> dense(nk), Uf(nk), Vf(nk);
+        std::vector<int> rk(nk, -1);
+        std::vector<std::array<double, 9>> R0s;
+        if (L.hf) {
+            R0s.resize(L.nwedge);
+            for (int z = 0; z < L.nwedge; ++z) R0s[z] = L.frames[z].R;  // canonical wedges have g = I
+        }
+        const double leps = lr_eps(P);
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int key = 0; key < nk; ++key) {
+            const auto &ki = P.m2l_keyinfo[l][key];
+            std::vector<double> Xb, Xa;  // source (C) and target (B) equivalent points
+            double off[3] = {ki[1] * L.w, ki[2] * L.w, ki[3] * L.w};
+            if (L.hf) {
+                rotate(R0s[ki[0]], T.X, Xb);
+                Xa.resize(Xb.size());
+                for (size_t t = 0; t < Xb.size() / 3; ++t)
+                    for (int d = 0; d < 3; ++d) Xa[3 * t + d] = off[d] - Xb[3 * t + d];
+            } else {
+                Xb = T.X;
+                Xa.resize(Xb.size());
+                for (size_t t = 0; t < Xb.size() / 3; ++t)
+                    for (int d = 0; d < 3; ++d) Xa[3 * t + d] = off[d] + Xb[3 * t + d];
+            }
+            CMat K(nx, nx);
+            for (int j = 0; j < nx; ++j)
+                for (int i = 0; i < nx; ++i) K(i, j) = kernel_G(&Xa[3 * i], &Xb[3 * j], P.k);
+            CMat KV = matmul(K, 'N', T.Vt, 'N');
+            CMat Kt = matmul(T.Vt, 'T', KV, 'N');  // s x s
+            SVD d = svd(Kt);
+            const int r = truncation_rank(d.s, leps);
+            if (2 * r < s) {
+                CMat U(s, r), V(r, s);
+                for (int c = 0; c < r; ++c) {
+                    for (int i = 0; i < s; ++i) U(i, c) = d.U(i, c);
+                    for (int j = 0; j < s; ++j) V(c, j) = d.s[c] * std::conj(d.V(j, c));
+                }
+                Uf[key] = std::move(U);
+                Vf[key] = std::move(V);
+                rk[key] = r;
+            } else {
+                dense[key] = std::move(Kt);
+            }
+        }
+        std::vector<int64_t> key_off(nk);
+        for (int key = 0; key < nk; ++key) {
+            if (rk[key] >= 0) {
+                key_off[key] = push_matrix(P, Uf[key]);
+                push_matrix(P, Vf[key]);
+            } else
+                key_off[key] = push_matrix(P, dense[key]);
+        }
+        GemvList &G = P.m2l_lists[l];
+        G.rows = G.cols = s;
+        G.ptr.push_back(0);
+        const auto &V = P.m2l[l];
+        for (size_t q = 0; q < V.size(); ++q) {
+            if (q == 0 || V[q].tgt_slot != V[q - 1].tgt_slot) {
+                if (q > 0) G.ptr.push_back((int)G.in_off.size());
+                G.out_off.push_back(L.in_base + (int64_t)V[q].tgt_slot * s);
+            }
+            G.in_off.push_back(L.out_base + (int64_t)V[q].src_slot * s);
+            G.mat_off.push_back(key_off[V[q].key]);
+            G.rank.push_back(rk[V[q].key]);
+        }
+        if (!V.empty()) G.ptr.push_back((int)G.in_off.size());
+    }
+
+    // ---- M2M (upward) and L2L (downward) between level l (parent) and l+1
+    P.m2m_lists.assign(nlev, GemvList());
+    P.l2l_lists.assign(nlev, GemvList());
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const LevelInfo &Lp = P.levels[l], &Lc = P.levels[l + 1];
+        const LevelTemplate &Tp = P.tmpl[l], &Tc = P.tmpl[l + 1];
+        if (Lp.n_out + Lp.n_in == 0) continue;
+        // collect the (parent wedge, octant) operators needed
+        std::map<std::pair<int, int>, int64_t> mats;
+        auto need = [&](int zp, int oct) { mats.emplace(std::make_pair(zp, oct), -1); };
+        for (size_t a = 0; a < Lp.cubes.size(); ++a) {
+            const Cube &Par = P.cubes[Lp.cubes[a]];
+            for (int zp = 0; zp < Lp.nwedge; ++zp) {
+                const bool po = Lp.out_slot[a * Lp.nwedge + zp] >= 0;
+                const bool pi = Lp.in_slot[a * Lp.nwedge + zp] >= 0;
+                if (!po && !pi) continue;
+                for (int o = 0; o < 8; ++o)
+                    if (Par.child[o] >= 0) need(zp, o);
+            }
+        }
+        std::vector<std::pair<int, int>> keys;
+        for (auto &kv : mats) keys.push_back(kv.first);
+        std::vector<CMat> Ms(keys.size());
+#pragma omp parallel for schedule(dynamic, 4)
+        for (size_t q = 0; q < keys.size(); ++q) {
+            const int zp = keys[q].first, oct = keys[q].second;
+            std::vector<double> Yp, Xc;
+            if (Lp.hf)
+                rotate(Lp.frames[zp].R, Tp.Y, Yp);
+            else
+                Yp = Tp.Y;
+            const int zc = Lc.hf ? wedge_child(zp, Lp.m) : 0;
+            if (Lc.hf)
+                rotate(Lc.frames[zc].R, Tc.X, Xc);
+            else
+                Xc = Tc.X;
+            const double wc = Lc.w;
+            const double off[3] = {((oct & 1) - 0.5) * wc, (((oct >> 1) & 1) - 0.5) * wc, (((oct >> 2) & 1) - 0.5) * wc};
+            for (size_t t = 0; t < Xc.size() / 3; ++t)
+                for (int d = 0; d < 3; ++d) Xc[3 * t + d] += off[d];
+            const int ny = (int)Yp.size() / 3, nx = (int)Xc.size() / 3;
+            CMat E(ny, nx);
+            for (int j = 0; j < nx; ++j)
+                for (int i = 0; i < ny; ++i) E(i, j) = kernel_G(&Yp[3 * i], &Xc[3 * j], P.k);
+            CMat EV = matmul(E, 'N', Tc.Vt, 'N');
+            Ms[q] = matmul(Tp.W, 'N', EV, 'N');  // s_p x s_c
+        }
+        for (size_t q = 0; q < keys.size(); ++q) mats[keys[q]] = push_matrix(P, Ms[q]);
+        // upward list: parent out slots
+        GemvList &U = P.m2m_lists[l];
+        U.rows = Tp.s;
+        U.cols = Tc.s;
+        U.ptr.push_back(0);
+        // downward list: child in slots
+        GemvList &D = P.l2l_lists[l + 1];
+        D.rows = Tc.s;
+        D.cols = Tp.s;
+        D.trans = 1;
+        D.ptr.push_back(0);
+        for (size_t a = 0; a < Lp.cubes.size(); ++a) {
+            const Cube &Par = P.cubes[Lp.cubes[a]];
+            for (int zp = 0; zp < Lp.nwedge; ++zp) {
+                const int so = Lp.out_slot[a * Lp.nwedge + zp];
+                if (so < 0) continue;
+                const int zc = Lc.hf ? wedge_child(zp, Lp.m) : 0;
+                U.out_off.push_back(Lp.out_base + (int64_t)so * Tp.s);
+                for (int o = 0; o < 8; ++o) {
+                    if (Par.child[o] < 0) continue;
+                    const Cube &Ch = P.cubes[Par.child[o]];
+                    const int cs = Lc.out_slot[(size_t)Ch.local * Lc.nwedge + zc];
+                    if (cs < 0) throw std::runtime_error("missing child outgoing slot");
+                    U.in_off.push_back(Lc.out_base + (int64_t)cs * Tc.s);
+                    U.mat_off.push_back(mats[{zp, o}]);
+                    U.rank.push_back(-1);
+                }
+                U.ptr.push_back((int)U.in_off.size());
+            }
+        }
+        // child in slots: gather parent wedges that map into them
+        for (size_t a = 0; a < Lc.cubes.size(); ++a) {
+            const Cube &Ch = P.cubes[Lc.cubes[a]];
+            if (Ch.parent < 0) continue;
+            const Cube &Par = P.cubes[Ch.parent];
+            int oct = -1;
+            for (int o = 0; o < 8; ++o)
+                if (Par.child[o] == Lc.cubes[a]) oct = o;
+            for (int zc = 0; zc < Lc.nwedge; ++zc) {
+                const int si = Lc.in_slot[a * Lc.nwedge + zc];
+                if (si < 0) continue;
+                std::vector<std::pair<int64_t, int64_t>> ent;
+                for (int zp = 0; zp < Lp.nwedge; ++zp) {
+                    const int ps = Lp.in_slot[(size_t)Par.local * Lp.nwedge + zp];
+                    if (ps < 0) continue;
+                    const int zcc = Lc.hf ? wedge_child(zp, Lp.m) : 0;
+                    if (zcc != zc) continue;
+                    ent.push_back({Lp.in_base + (int64_t)ps * Tp.s, mats[{zp, oct}]});
+                }
+                if (ent.empty()) continue;
+                D.out_off.push_back(Lc.in_base + (int64_t)si * Tc.s);
+                for (auto &e : ent) {
+                    D.in_off.push_back(e.first);
+                    D.mat_off.push_back(e.second);
+                    D.rank.push_back(-1);
+                }
+                D.ptr.push_back((int)D.in_off.size());
+            }
+        }
+    }
+
+    // ---- leaf tasks
+    P.s2m_tasks.clear();
+    P.l2t_tasks.clear();
+    P.max_Y_leaf = 0;
+    for (int id : P.leaves) {
+        const Cube &c = P.cubes[id];
+        const LevelInfo &L = P.levels[c.level];
+        if (L.hf) {
+            bool any = false;
+            for (int z = 0; z < L.nwedge; ++z)
+                any |= L.out_slot[(size_t)c.local * L.nwedge + z] >= 0 || L.in_slot[(size_t)c.local * L.nwedge + z] >= 0;
+            if (any) throw std::runtime_error("high-frequency leaves are not supported by this leaf rule");
+            continue;
+        }
+        const int so = L.out_slot[c.local], si = L.in_slot[c.local];
+        const int s = P.tmpl[c.level].s;
+        LeafTask t;
+        t.start = c.start;
+        t.end = c.end;
+        t.tmpl = c.level;
+        for (int d = 0; d < 3; ++d) t.center[d] = P.root_center[d] - 0.5 * P.root_w + (c.ijk[d] + 0.5) * L.w;
+        if (so >= 0) {
+            t.slot_off = L.out_base + (int64_t)so * s;
+            P.s2m_tasks.push_back(t);
+        }
+        if (si >= 0) {
+            t.slot_off = L.in_base + (int64_t)si * s;
+            P.l2t_tasks.push_back(t);
+        }
+        if (so >= 0 || si >= 0) P.max_Y_leaf = std::max(P.max_Y_leaf, (int)P.tmpl[c.level].Y.size() / 3);
+    }
+}
+
+}  // namespace fdbem

@@ -1,0 +1,129 @@
+"""Thin Python binding over the C ABI: argument marshalling only.  Device
+memory and streams come from PyTorch; every step of the mat-vec and solver
+runs in the library's HIP kernels."""
+
+from __future__ import annotations
+
+import ctypes
+import json
+
+import numpy as np
+
+from . import _abi
+
+
+def nystrom_nodes(elements: np.ndarray):
+    """Nodes, normals (into the body) and weights of the six-point rule on each
+    curved quadratic element (bem_nystrom_nodes)."""
+    el = np.ascontiguousarray(elements, dtype=np.float64).reshape(-1, 6, 3)
+    ne = el.shape[0]
+    pts = np.empty((6 * ne, 3))
+    nrm = np.empty((6 * ne, 3))
+    w = np.empty(6 * ne)
+    _abi.check(_abi.lib().bem_nystrom_nodes(ne, el.ctypes.data, pts.ctypes.data, nrm.ctypes.data, w.ctypes.data))
+    return pts, nrm, w
+
+
+def _stream_ptr(stream):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_vec(t, n):
+    import torch
+
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()
+            and t.numel() == n):
+        raise ValueError(f"expected a contiguous complex128 CUDA tensor of length {n}")
+
+
+class Plan:
+    """A built fast directional Burton-Miller operator on the current GPU."""
+
+    def __init__(self, pts, nrm, w, k: float, eps: float, elements=None, **opts):
+        L = _abi.lib()
+        self._pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        self._nrm = np.ascontiguousarray(nrm, dtype=np.float64).reshape(-1, 3)
+        self._w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+        self.n = int(self._w.shape[0])
+        self.k = float(k)
+        self.eps = float(eps)
+        el = None if elements is None else np.ascontiguousarray(elements, dtype=np.float64).reshape(-1, 6, 3)
+        g = _abi.FdaGeometry(self.n, self._pts.ctypes.data, self._nrm.ctypes.data, self._w.ctypes.data,
+                             0 if el is None else el.shape[0], None if el is None else el.ctypes.data)
+        o = _abi.FdaOpts()
+        _abi.check(L.fda_default_opts(ctypes.byref(o)))
+        for key, val in opts.items():
+            if not hasattr(o, key):
+                raise TypeError(f"unknown option {key}")
+            setattr(o, key, val)
+        h = ctypes.c_void_p()
+        _abi.check(L.fda_build(ctypes.byref(g), self.k, self.eps, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _abi.lib().fda_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matvec(self, u, op: str = "RAW_H", out=None, stream=None):
+        import torch
+
+        _check_vec(u, self.n)
+        if out is None:
+            out = torch.empty_like(u)
+        _check_vec(out, self.n)
+        _abi.check(_abi.lib().fda_matvec(self._h, _abi.OPS[op], ctypes.c_void_p(u.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def rhs_plane_wave(self, d, stream=None):
+        import torch
+
+        out = torch.empty(self.n, dtype=torch.complex128, device="cuda")
+        dd = (ctypes.c_double * 3)(*[float(v) for v in d])
+        _abi.check(_abi.lib().fda_rhs_plane_wave(self._h, dd, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def solve(self, rhs, tol: float, maxit: int = 200, restart: int = 200, op: str = "BM_H", precond: int = 0,
+              stream=None, raise_on_fail: bool = True):
+        import torch
+
+        _check_vec(rhs, self.n)
+        x = torch.empty_like(rhs)
+        it = ctypes.c_int(0)
+        rel = ctypes.c_double(0)
+        hist = np.zeros(maxit + 1)
+        rc = _abi.lib().bm_solve(self._h, _abi.OPS[op], ctypes.c_void_p(rhs.data_ptr()), float(tol), int(maxit),
+                                 int(restart), int(precond), ctypes.c_void_p(x.data_ptr()), ctypes.byref(it),
+                                 ctypes.byref(rel), hist.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream))
+        info = {"status": rc, "iterations": it.value, "relres": rel.value, "history": hist[: it.value + 1].copy()}
+        if rc != _abi.FDA_OK and raise_on_fail:
+            _abi.check(rc)
+        return x, info
+
+    def set_timing(self, on: bool = True):
+        _abi.check(_abi.lib().fda_set_timing(self._h, 1 if on else 0))
+
+    def phase_times(self):
+        buf = (ctypes.c_double * 8)()
+        _abi.check(_abi.lib().fda_phase_times(self._h, buf, 8))
+        names = ("p2p", "s2m", "m2m", "m2l", "l2l", "l2t", "near_corr", "permute")
+        return dict(zip(names, list(buf)))
+
+    def stats(self) -> dict:
+        buf = ctypes.create_string_buffer(1 << 20)
+        _abi.check(_abi.lib().fda_stats(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+
+def build(pts, nrm, w, k, eps, elements=None, **opts) -> Plan:
+    return Plan(pts, nrm, w, k, eps, elements=elements, **opts)

@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every entry point the public header declares, rejects bad arguments before
+touching a device, and its Nystrom discretisation matches the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1311_5202_amd as fdb
+from paper_1311_5202_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "fdbem.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fdb.lib()
+    names = _declared()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(_abi.EXPORTS)
+
+
+def test_default_options():
+    o = _abi.FdaOpts()
+    assert fdb.lib().fda_default_opts(ctypes.byref(o)) == 0
+    assert o.leaf_cap == 64 and o.far_field == 1 and abs(o.c_d - 1 / np.pi) < 1e-15
+
+
+def _geom(n):
+    pts = np.random.default_rng(0).standard_normal((n, 3))
+    nrm = pts / np.linalg.norm(pts, axis=1, keepdims=True)
+    return pts, nrm, np.ones(n)
+
+
+@pytest.mark.parametrize("k,eps", [(0.0, 1e-4), (-1.0, 1e-4), (5.0, 0.0), (5.0, 1.5), (float("nan"), 1e-4)])
+def test_build_rejects_bad_arguments(k, eps):
+    pts, nrm, w = _geom(10)
+    with pytest.raises(_abi.FdaError) as e:
+        fdb.build(pts, nrm, w, k, eps)
+    assert e.value.code == _abi.FDA_EINVAL
+
+
+def test_build_rejects_empty_and_mismatched_elements():
+    with pytest.raises(_abi.FdaError) as e:
+        fdb.build(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), 5.0, 1e-4)
+    assert e.value.code == _abi.FDA_EINVAL
+    pts, nrm, w = _geom(10)
+    with pytest.raises(_abi.FdaError) as e:
+        fdb.build(pts, nrm, w, 5.0, 1e-4, elements=np.zeros((3, 6, 3)))
+    assert e.value.code == _abi.FDA_EINVAL
+    msg = fdb.lib().fda_last_error().decode()
+    assert "element" in msg
+
+
+def test_null_arguments():
+    L = fdb.lib()
+    assert L.fda_matvec(None, 0, None, None, None) == _abi.FDA_EINVAL
+    assert L.bem_nystrom_nodes(0, None, None, None, None) == _abi.FDA_EINVAL
+    assert L.fda_stats(None, None, 0) == _abi.FDA_EINVAL
+    L.fda_destroy(None)
+
+
+def test_nystrom_nodes_match_oracle():
+    import synth
+    from oracle import quadrature as q
+
+    for el in (synth.octa_sphere(5), synth.ellipsoid(3, 2.5), synth.star_surface(4, seed=3)):
+        p, n, w = fdb.nystrom_nodes(el)
+        p2, n2, w2 = q.nystrom_nodes(el)
+        assert np.max(np.abs(p - p2)) < 1e-14
+        assert np.max(np.abs(n - n2)) < 1e-13
+        assert np.max(np.abs(w - w2)) < 1e-15 * 10

@@ -1,0 +1,103 @@
+"""GPU parity of the fast directional mat-vec against the oracle's dense
+FP64 sums (section 4.1 error measure: relative L2 over target rows)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+OPS = (("RAW_H", "H"), ("RAW_G", "G"), ("RAW_T1", "T1"))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available()
+    return t
+
+
+def _geom(n):
+    import paper_1311_5202_amd as fdb
+
+    el = synth.octa_sphere(n)
+    pts, nrm, w = fdb.nystrom_nodes(el)
+    return el, pts, nrm, w
+
+
+def _run(torch, plan, u, op):
+    return plan.matvec(torch.from_numpy(u).cuda(), op).cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [3, 8])
+def test_direct_sum_equals_oracle(torch, n):
+    """far_field = 0: one leaf, every pair by the P2P kernel (ragged tiles at n = 3)."""
+    import paper_1311_5202_amd as fdb
+
+    _, pts, nrm, w = _geom(n)
+    k = 5.0
+    print(f"[direct] N={len(w)} k={k}", flush=True)
+    plan = fdb.build(pts, nrm, w, k, 1e-4, far_field=0)
+    u = synth.random_densities(len(w), 0)
+    for op, oop in OPS:
+        got = _run(torch, plan, u, op)
+        ref = oracle.dense_rows(pts, nrm, w, u, k, oop)
+        assert oracle.rel_l2(got, ref) < 1e-13, op
+        assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref)), op
+    plan.close()
+
+
+def test_fda_small_sphere_all_rows(torch):
+    """N = 3072, k = 5 (low-frequency levels only): every row within 1e-4."""
+    import paper_1311_5202_amd as fdb
+
+    _, pts, nrm, w = _geom(8)
+    k = 5.0
+    print(f"[fda-lf] N={len(w)} k={k}", flush=True)
+    plan = fdb.build(pts, nrm, w, k, 1e-4)
+    u = synth.random_densities(len(w), 0)
+    for op, oop in OPS:
+        got = _run(torch, plan, u, op)
+        ref = oracle.dense_rows(pts, nrm, w, u, k, oop)
+        err = oracle.rel_l2(got, ref)
+        print(op, err)
+        assert err <= 1e-4, op
+    st = plan.stats()
+    assert st["N"] == len(w)
+    plan.close()
+
+
+def test_fda_high_frequency_sampled_rows(torch):
+    """N = 27,648, k = 25: one high-frequency (directional) level plus two
+    low-frequency levels; 400 seeded rows against the oracle."""
+    import paper_1311_5202_amd as fdb
+
+    _, pts, nrm, w = _geom(24)
+    k = 25.0
+    print(f"[fda-hf] N={len(w)} k={k}", flush=True)
+    plan = fdb.build(pts, nrm, w, k, 1e-4)
+    st = plan.stats()
+    assert any(L["hf"] and L["m2l_pairs"] > 0 for L in st["levels"])
+    u = synth.random_densities(len(w), 1)
+    rows = np.sort(np.random.default_rng(7).choice(len(w), 400, replace=False))
+    for op, oop in OPS:
+        got = _run(torch, plan, u, op)
+        ref = oracle.dense_rows(pts, nrm, w, u, k, oop, rows=rows)
+        err = oracle.rel_l2(got[rows], ref)
+        print(op, err)
+        assert err <= 1e-4, op
+    plan.close()
+
+
+def test_repeated_matvec_is_deterministic(torch):
+    import paper_1311_5202_amd as fdb
+
+    _, pts, nrm, w = _geom(6)
+    plan = fdb.build(pts, nrm, w, 8.0, 1e-4)
+    u = torch.from_numpy(synth.random_densities(len(w), 3)).cuda()
+    a = plan.matvec(u, "RAW_H").cpu().numpy()
+    b = plan.matvec(u, "RAW_H").cpu().numpy()
+    assert np.array_equal(a, b)
+    plan.close()
