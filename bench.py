@@ -1,0 +1,153 @@
+"""Benchmark: fast directional Burton-Miller mat-vecs per second on one GPU.
+
+One "step" is one full sound-hard Burton-Miller H mat-vec through the C ABI
+(near-field P2P, S2M, M2M, M2L, L2L, L2T and, when the plan has elements,
+the near-field correction), on seeded random complex densities already
+resident in HBM.  Plan construction is not timed.
+
+Prints one JSON line (rank 0) with the metric, the roofline of the dominant
+kernel and the oracle's CPU baseline on a bounded sample of rows.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (octahedral split n, k, eps, description)
+    "c1": (8, 5.0, 1e-4, "unit sphere, 512 quadratic triangles, N=3072, k=5 (kD=10), eps=1e-4"),
+    "c2": (64, 50.0, 1e-4, "unit sphere, 32768 quadratic triangles, N=196608, k=50 (kD=100), eps=1e-4, leaf<=64"),
+    "c5": (289, 500.0, 1e-4, "unit sphere, 668168 quadratic triangles, N=4009008, k=500 (kD=1000), eps=1e-4"),
+}
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
+PEAK_HBM_GBS = 8000.0
+
+
+def m2l_work(plan_stats: dict) -> tuple[float, float]:
+    """Algorithmic FP64 flops and HBM bytes of the M2L phase of one mat-vec:
+    a dense compressed operator costs 8 s^2 real flops per pair, a rank-r
+    factorised one 16 r s; bytes count each unique operator once, each source
+    slot read per pair and each target slot read and written once."""
+    flops = 0.0
+    byts = 0.0
+    for L in plan_stats["levels"]:
+        s = L["s"]
+        flops += L.get("m2l_flops", 8.0 * s * s * L["m2l_pairs"])
+        byts += L.get("m2l_op_bytes", 0) + 16.0 * s * L["m2l_pairs"] + 32.0 * s * L["in_slots"]
+    return flops, byts
+
+
+def cpu_baseline(pts, nrm, w, u, k, n_rows: int):
+    import numpy as np
+
+    import oracle
+
+    rows = np.sort(np.random.default_rng(7).choice(len(w), n_rows, replace=False))
+    oracle.dense_rows(pts[:64], nrm[:64], w[:64], u[:64], k, "H", rows=np.arange(4))  # load + warm
+    t0 = time.perf_counter()
+    oracle.dense_rows(pts, nrm, w, u, k, "H", rows=rows)
+    dt = time.perf_counter() - t0
+    full = dt * len(w) / n_rows
+    return {"value": 1.0 / full, "unit": "matvec/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"dense FP64 H sum on {n_rows} of {len(w)} target rows ({dt:.1f} s), scaled to a full mat-vec"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=os.environ.get("FDBEM_WORKLOAD", "c2"), choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        return 2
+    import numpy as np
+    import torch
+
+    import paper_1311_5202_amd as fdb
+    import synth
+
+    n_split, k, eps, desc = WORKLOADS[args.workload]
+    el = synth.octa_sphere(n_split)
+    pts, nrm, w = fdb.nystrom_nodes(el)
+    N = len(w)
+    t0 = time.perf_counter()
+    plan = fdb.build(pts, nrm, w, k, eps)
+    t_build = time.perf_counter() - t0
+    st = plan.stats()
+    print(f"[bench] workload={args.workload} N={N} k={k} build {t_build:.1f} s", file=sys.stderr, flush=True)
+    u_host = synth.random_densities(N, 1)
+    u = torch.from_numpy(u_host).cuda()
+    out = torch.empty_like(u)
+    op = "BM_H" if st.get("corr_nnz", 0) > 0 else "RAW_H"
+    for _ in range(args.warmup):
+        plan.matvec(u, op, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.matvec(u, op, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # per-phase HIP-event times over a second pass of the same steps
+    plan.set_timing(True)
+    for _ in range(args.steps):
+        plan.matvec(u, op, out=out)
+    phases = plan.phase_times()
+    plan.set_timing(False)
+    torch.cuda.synchronize()
+    ms = 1e3 * dt / args.steps
+    flops, byts = m2l_work(st)
+    m2l_ms = phases["m2l"]
+    n_m2l_launch = max(1, sum(1 for L in st["levels"] if L["m2l_pairs"] > 0))
+    roof = {
+        "bound": "mfma",
+        "kernel": "k_gemv<M2L> (all levels of one mat-vec)",
+        "achieved": flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else 0.0,
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "traffic": None,
+        "launches_per_matvec": n_m2l_launch,
+        "algorithmic_flops_per_matvec": flops,
+        "algorithmic_bytes_per_matvec": byts,
+    }
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    res = {
+        "metric": "FDA matvecs/s (Burton-Miller H operator)",
+        "value": args.steps / dt,
+        "unit": "matvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "N": N, "k": k, "eps": eps, "operator": op, "parallelism": "single GPU"},
+        "phase_ms": phases,
+        "build_s": t_build,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        n_rows = args.cpu_rows or max(64, min(N, int(2.5e9 / N)))
+        res["cpu_baseline"] = cpu_baseline(pts, nrm, w, u_host, k, n_rows)
+    plan.close()
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

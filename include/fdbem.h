@@ -126,12 +126,15 @@ int fda_rhs_plane_wave(fda_plan *plan, const double d[3], void *rhs_dev, void *h
  * including the terminating zero; returns FDA_EINVAL if it does not fit. */
 int fda_stats(const fda_plan *plan, char *json_buf, size_t len);
 
-/* Enable (1) or disable (0) per-phase HIP-event timing of fda_matvec. */
+/* Enable (1) or disable (0) per-phase HIP-event timing of fda_matvec.  Events
+ * are recorded on the mat-vec's stream without synchronising. */
 int fda_set_timing(fda_plan *plan, int on);
 
-/* Per-phase times (milliseconds) of the last timed mat-vec, in the order
- * P2P, S2M, M2M, M2L, L2L, L2T, near correction, permutations.  n: capacity. */
-int fda_phase_times(const fda_plan *plan, double *ms, int n);
+/* Per-phase times (milliseconds), averaged over the timed mat-vecs since the
+ * previous call (at most the last 64), in the order P2P, S2M, M2M, M2L, L2L,
+ * L2T, near correction, permutations; n: capacity of ms.  Waits for the
+ * recorded events, then starts a new averaging window. */
+int fda_phase_times(fda_plan *plan, double *ms, int n);
 
 /* Release every device and host resource of the plan (NULL is allowed). */
 void fda_destroy(fda_plan *plan);

@@ -186,10 +186,11 @@ int fda_set_timing(fda_plan *plan, int on)
     });
 }
 
-int fda_phase_times(const fda_plan *plan, double *ms, int n)
+int fda_phase_times(fda_plan *plan, double *ms, int n)
 {
     return guarded([&] {
         if (!plan || !ms || n < 0) throw std::invalid_argument("null argument");
+        device_phase_average(*plan->P);
         for (int t = 0; t < n && t < 8; ++t) ms[t] = plan->P->dev->phase_ms[t];
         return FDA_OK;
     });

@@ -267,6 +267,8 @@ __global__ __launch_bounds__(LEAF_BLOCK) void k_l2t(const int64_t *__restrict__ 
 // Batched segmented GEMV: out[o] += sum_e op(M_e) in[e]; one block per output slot.
 constexpr int GEMV_BLOCK = 128;
 constexpr int GEMV_MAXROWS = 2 * GEMV_BLOCK;
+enum { TAG_M2M = 0, TAG_M2L = 1, TAG_L2L = 2 };
+template <int TAG>
 __global__ __launch_bounds__(GEMV_BLOCK) void k_gemv(const int64_t *__restrict__ out_off, const int *__restrict__ ptr,
                                                      const int64_t *__restrict__ in_off,
                                                      const int64_t *__restrict__ mat_off, const int *__restrict__ rank,
@@ -481,6 +483,7 @@ void device_upload(Plan &P)
         for (size_t i = 0; i < cv.size(); ++i) cv[i] = make_double2(P.corr_val[i].real(), P.corr_val[i].imag());
         D.corr_val = dupload(D, cv);
     }
+    D.ev.assign((size_t)Device::kRing * 10, nullptr);
     for (auto &e : D.ev) HIP_CHECK(hipEventCreate(&e));
 }
 
@@ -521,11 +524,12 @@ static OpC op_coef(int op, double k)
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+template <int TAG>
 static void run_gemv(const DGemv &g, const double2 *mat, const double2 *in, double2 *out, hipStream_t st)
 {
     if (g.n_out == 0) return;
     const size_t shm = sizeof(double2) * (g.cols + std::max(g.max_rank, 1));
-    hipLaunchKernelGGL(k_gemv, dim3(g.n_out), dim3(GEMV_BLOCK), shm, st, g.out_off, g.ptr, g.in_off, g.mat_off, g.rank,
+    hipLaunchKernelGGL(k_gemv<TAG>, dim3(g.n_out), dim3(GEMV_BLOCK), shm, st, g.out_off, g.ptr, g.in_off, g.mat_off, g.rank,
                        g.rows, g.cols, g.trans, mat, in, out);
 }
 
@@ -536,12 +540,13 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
     const OpC c = op_coef(op, P.k);
     const bool bm = (op == 3 || op == 4);
     const bool tm = D.timing != 0;
-    if (tm) HIP_CHECK(hipEventRecord(D.ev[0], st));
+    hipEvent_t *ev = tm ? &D.ev[(size_t)(D.ring_pos % Device::kRing) * 10] : nullptr;
+    if (tm) HIP_CHECK(hipEventRecord(ev[0], st));
     hipLaunchKernelGGL(k_permute_in, dim3(nblk(N, 256)), dim3(256), 0, st, in, D.perm, D.w, D.dens, N);
-    if (tm) HIP_CHECK(hipEventRecord(D.ev[1], st));
+    if (tm) HIP_CHECK(hipEventRecord(ev[1], st));
     hipLaunchKernelGGL(k_p2p, dim3(D.n_leaf), dim3(P2P_TILE), 0, st, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
                        D.x, D.y, D.z, D.nx, D.ny, D.nz, D.dens, D.res, P.k, c);
-    if (tm) HIP_CHECK(hipEventRecord(D.ev[2], st));
+    if (tm) HIP_CHECK(hipEventRecord(ev[2], st));
     if (P.opt.far_field) {
         if (D.n_od) hipLaunchKernelGGL(k_fill_zero, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, D.od, D.n_od);
         if (D.n_id) hipLaunchKernelGGL(k_fill_zero, dim3(nblk(D.n_id, 256)), dim3(256), 0, st, D.id, D.n_id);
@@ -550,41 +555,57 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
             hipLaunchKernelGGL(k_s2m, dim3(D.s2m.n), dim3(LEAF_BLOCK), shm_leaf, st, D.s2m.start, D.s2m.end,
                                D.s2m.slot, D.s2m.tmpl, D.s2m.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, D.t_W,
                                D.x, D.y, D.z, D.nx, D.ny, D.nz, D.dens, D.od, P.k, c);
-        if (tm) HIP_CHECK(hipEventRecord(D.ev[3], st));
-        for (int l = D.n_lev - 2; l >= 0; --l) run_gemv(D.m2m[l], D.mat, D.od, D.od, st);
-        if (tm) HIP_CHECK(hipEventRecord(D.ev[4], st));
-        for (int l = 0; l < D.n_lev; ++l) run_gemv(D.m2l[l], D.mat, D.od, D.id, st);
-        if (tm) HIP_CHECK(hipEventRecord(D.ev[5], st));
-        for (int l = 1; l < D.n_lev; ++l) run_gemv(D.l2l[l], D.mat, D.id, D.id, st);
-        if (tm) HIP_CHECK(hipEventRecord(D.ev[6], st));
+        if (tm) HIP_CHECK(hipEventRecord(ev[3], st));
+        for (int l = D.n_lev - 2; l >= 0; --l) run_gemv<TAG_M2M>(D.m2m[l], D.mat, D.od, D.od, st);
+        if (tm) HIP_CHECK(hipEventRecord(ev[4], st));
+        for (int l = 0; l < D.n_lev; ++l) run_gemv<TAG_M2L>(D.m2l[l], D.mat, D.od, D.id, st);
+        if (tm) HIP_CHECK(hipEventRecord(ev[5], st));
+        for (int l = 1; l < D.n_lev; ++l) run_gemv<TAG_L2L>(D.l2l[l], D.mat, D.id, D.id, st);
+        if (tm) HIP_CHECK(hipEventRecord(ev[6], st));
         if (D.l2t.n)
             hipLaunchKernelGGL(k_l2t, dim3(D.l2t.n), dim3(LEAF_BLOCK), shm_leaf, st, D.l2t.start, D.l2t.end,
                                D.l2t.slot, D.l2t.tmpl, D.l2t.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, D.t_W,
                                D.x, D.y, D.z, D.nx, D.ny, D.nz, D.id, D.res, P.k, c);
     } else if (tm) {
-        for (int e = 3; e <= 6; ++e) HIP_CHECK(hipEventRecord(D.ev[e], st));
+        for (int e = 3; e <= 6; ++e) HIP_CHECK(hipEventRecord(ev[e], st));
     }
-    if (tm) HIP_CHECK(hipEventRecord(D.ev[7], st));
+    if (tm) HIP_CHECK(hipEventRecord(ev[7], st));
     hipLaunchKernelGGL(k_permute_out, dim3(nblk(N, 256)), dim3(256), 0, st, D.res, D.perm, in, bm ? 0.5 : 0.0, out, N);
-    if (tm) HIP_CHECK(hipEventRecord(D.ev[8], st));
+    if (tm) HIP_CHECK(hipEventRecord(ev[8], st));
     if (bm && D.corr_nnz)
         hipLaunchKernelGGL(k_corr, dim3(nblk(N, 256)), dim3(256), 0, st, D.corr_ptr, D.corr_col, D.corr_val, in, out, N);
     if (tm) {
-        HIP_CHECK(hipEventRecord(D.ev[9], st));
-        HIP_CHECK(hipEventSynchronize(D.ev[9]));
-        float ms;
-        // P2P, S2M, M2M, M2L, L2L, L2T, correction, permutations
-        const int a[8] = {1, 2, 3, 4, 5, 6, 8, 0}, b[8] = {2, 3, 4, 5, 6, 7, 9, 1};
-        for (int t = 0; t < 7; ++t) {
-            HIP_CHECK(hipEventElapsedTime(&ms, D.ev[a[t]], D.ev[b[t]]));
-            D.phase_ms[t] = ms;
-        }
-        float m0, m1;
-        HIP_CHECK(hipEventElapsedTime(&m0, D.ev[0], D.ev[1]));
-        HIP_CHECK(hipEventElapsedTime(&m1, D.ev[7], D.ev[8]));
-        D.phase_ms[7] = m0 + m1;
+        HIP_CHECK(hipEventRecord(ev[9], st));
+        D.ring_pos++;
+        D.ring_count++;
     }
     HIP_CHECK(hipGetLastError());
+}
+
+// Average the per-phase times of the timed mat-vecs recorded since the last
+// call (at most the ring size), then start a new window.
+void device_phase_average(Plan &P)
+{
+    Device &D = *P.dev;
+    const int n = std::min(D.ring_count, Device::kRing);
+    for (int t = 0; t < 8; ++t) D.phase_ms[t] = 0.0;
+    if (n == 0) return;
+    const int a[8] = {1, 2, 3, 4, 5, 6, 8, 0}, b[8] = {2, 3, 4, 5, 6, 7, 9, 1};
+    for (int q = 0; q < n; ++q) {
+        const int slot = (D.ring_pos - 1 - q + Device::kRing * 4) % Device::kRing;
+        hipEvent_t *ev = &D.ev[(size_t)slot * 10];
+        HIP_CHECK(hipEventSynchronize(ev[9]));
+        float ms;
+        for (int t = 0; t < 7; ++t) {
+            HIP_CHECK(hipEventElapsedTime(&ms, ev[a[t]], ev[b[t]]));
+            D.phase_ms[t] += ms / n;
+        }
+        float m0, m1;
+        HIP_CHECK(hipEventElapsedTime(&m0, ev[0], ev[1]));
+        HIP_CHECK(hipEventElapsedTime(&m1, ev[7], ev[8]));
+        D.phase_ms[7] += (m0 + m1) / n;
+    }
+    D.ring_count = 0;
 }
 
 void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t st)

@@ -58,7 +58,9 @@ struct Device {
     double2 *gm_red_c = nullptr;
     // timing
     int timing = 0;
-    hipEvent_t ev[10] = {};
+    static constexpr int kRing = 64;     // timed mat-vecs kept for averaging
+    std::vector<hipEvent_t> ev;          // kRing x 10 events, recorded without synchronising
+    int ring_pos = 0, ring_count = 0;
     double phase_ms[8] = {0};
     std::vector<void *> allocs;
     size_t bytes = 0;
@@ -66,6 +68,7 @@ struct Device {
 
 void device_upload(Plan &P);
 void device_free(Plan &P);
+void device_phase_average(Plan &P);
 void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st);
 void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t st);
 int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int restart, int precond, double2 *x,

@@ -5,6 +5,8 @@
 #include <sstream>
 #include <stdexcept>
 
+#include <unordered_map>
+
 #include "plan.hpp"
 
 namespace fdbem {
@@ -90,14 +92,25 @@ std::string plan_stats(const Plan &P)
         const LevelInfo &L = P.levels[l];
         int64_t npairs = l < P.m2l.size() ? (int64_t)P.m2l[l].size() : 0;
         int nlr = 0, nk = l < P.m2l_nkeys.size() ? P.m2l_nkeys[l] : 0;
-        if (l < P.m2l_lists.size())
-            for (size_t q = 0; q < P.m2l_lists[l].rank.size(); ++q) nlr += P.m2l_lists[l].rank[q] >= 0;
+        double flops = 0, opbytes = 0;
+        if (l < P.m2l_lists.size()) {
+            const GemvList &G = P.m2l_lists[l];
+            std::unordered_map<int64_t, int> seen;
+            for (size_t q = 0; q < G.rank.size(); ++q) {
+                const int r = G.rank[q];
+                nlr += r >= 0;
+                flops += r >= 0 ? 8.0 * r * (G.rows + G.cols) : 8.0 * G.rows * G.cols;
+                if (seen.emplace(G.mat_off[q], r).second)
+                    opbytes += 16.0 * (r >= 0 ? (double)r * (G.rows + G.cols) : (double)G.rows * G.cols);
+            }
+        }
         o << (l ? ", " : "") << "{\"w\": " << L.w << ", \"hf\": " << (L.hf ? 1 : 0) << ", \"m\": " << L.m
           << ", \"cubes\": " << L.cubes.size() << ", \"out_slots\": " << L.n_out << ", \"in_slots\": " << L.n_in
           << ", \"s\": " << (l < P.tmpl.size() ? P.tmpl[l].s : 0)
           << ", \"n_equiv\": " << (l < P.tmpl.size() ? P.tmpl[l].X.size() / 3 : 0)
           << ", \"n_check\": " << (l < P.tmpl.size() ? P.tmpl[l].Y.size() / 3 : 0) << ", \"m2l_pairs\": " << npairs
-          << ", \"m2l_ops\": " << nk << ", \"m2l_pairs_lowrank\": " << nlr << "}";
+          << ", \"m2l_ops\": " << nk << ", \"m2l_pairs_lowrank\": " << nlr << ", \"m2l_flops\": " << flops
+          << ", \"m2l_op_bytes\": " << opbytes << "}";
     }
     o << "]}";
     return o.str();
