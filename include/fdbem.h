@@ -78,7 +78,7 @@ typedef struct {
     int far_field;      /* 1: fast directional far field; 0: all pairs summed directly    */
     int lf_grid;        /* points per edge of low-frequency surface grids; 0 -> from eps  */
     int precision;      /* FDA_PREC_FP64 or FDA_PREC_FP32 (far field and P2P in FP32)     */
-    int corrections;    /* 1: build the local corrections when elements are given        */
+    int corrections;    /* bit 0: corrected H table, bit 1: corrected G table (needs elements) */
     int verbose;
 } fda_opts;
 
@@ -91,6 +91,19 @@ int fda_default_opts(fda_opts *o);
  * and weights of the six-point degree-4 Gauss rule on each curved quadratic
  * element.  All host arrays; pts/nrm are 6*n_elem x 3, w is 6*n_elem. */
 int bem_nystrom_nodes(int64_t n_elem, const double *elem, double *pts, double *nrm, double *w);
+
+/* Locally corrected near-field table of one operator (section 2.2, eqs.
+ * near field, local correction, kcorrection), host only, caller node order:
+ * CSR rows i with entries dw_ij = wbar_j(K; x_i) - [j != i] w_j K(x_i, y_j)
+ * over the nodes j of the elements in the local region D_i of x_i (elements
+ * whose distance to x_i is at most twice their longest side).  op is
+ * FDA_OP_BM_H (K = dG/dn_y + alpha d2G/dn_x dn_y) or FDA_OP_BM_G
+ * (K = G + alpha dG/dn_x).  Call with row_ptr = col = val = NULL to get
+ * *nnz_out; then with row_ptr (n_nodes+1), col (nnz) and val (2*nnz doubles,
+ * interleaved complex) to fill them.  Nodes must be those of
+ * bem_nystrom_nodes for the same elements. */
+int bem_near_correction(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,
+                        double k, int op, int64_t *nnz_out, int64_t *row_ptr, int64_t *col, double *val);
 
 /* Build a plan on the current HIP device: octree and lists (section 3.1.1),
  * point templates and pseudo-inverses (section 3.1.2, eqs. eq_svdr/eq_invr),

@@ -108,3 +108,6 @@ def rel_l2(a, b) -> float:
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+from . import near  # noqa: E402,F401

@@ -19,7 +19,7 @@ FDA_ENOTSUP = -7
 
 OPS = {"RAW_H": 0, "RAW_G": 1, "RAW_T1": 2, "BM_H": 3, "BM_G": 4}
 
-EXPORTS = ("fda_default_opts", "bem_nystrom_nodes", "fda_build", "fda_matvec", "bm_solve", "fda_rhs_plane_wave",
+EXPORTS = ("fda_default_opts", "bem_nystrom_nodes", "bem_near_correction", "fda_build", "fda_matvec", "bm_solve", "fda_rhs_plane_wave",
            "fda_stats", "fda_set_timing", "fda_phase_times", "fda_destroy", "fda_last_error")
 
 
@@ -55,6 +55,7 @@ def lib() -> ctypes.CDLL:
     vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     L.fda_default_opts.argtypes = [ctypes.POINTER(FdaOpts)]
     L.bem_nystrom_nodes.argtypes = [i64, vp, vp, vp, vp]
+    L.bem_near_correction.argtypes = [i64, vp, vp, vp, vp, dbl, ci, ctypes.POINTER(i64), vp, vp, vp]
     L.fda_build.argtypes = [ctypes.POINTER(FdaGeometry), dbl, dbl, ctypes.POINTER(FdaOpts), ctypes.POINTER(vp)]
     L.fda_matvec.argtypes = [vp, ci, vp, vp, vp]
     L.bm_solve.argtypes = [vp, ci, vp, dbl, ci, ci, ci, vp, ctypes.POINTER(ci), ctypes.POINTER(dbl), vp, vp]

@@ -2,6 +2,7 @@
 // catches exceptions and turns them into status codes.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -79,6 +80,26 @@ int bem_nystrom_nodes(int64_t n_elem, const double *elem, double *pts, double *n
     });
 }
 
+int bem_near_correction(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,
+                        double k, int op, int64_t *nnz_out, int64_t *row_ptr, int64_t *col, double *val)
+{
+    return guarded([&] {
+        if (n_elem <= 0 || !elem || !pts || !nrm || !w || !nnz_out) throw std::invalid_argument("null argument");
+        if (!(k > 0) || !std::isfinite(k)) throw std::invalid_argument("wavenumber must be positive");
+        if (op != FDA_OP_BM_H && op != FDA_OP_BM_G) throw std::invalid_argument("op must be FDA_OP_BM_H or FDA_OP_BM_G");
+        std::vector<int64_t> rp, cl;
+        std::vector<cplx> vl;
+        correction_table_host(n_elem, elem, pts, nrm, w, k, op, rp, cl, vl);
+        *nnz_out = (int64_t)cl.size();
+        if (row_ptr && col && val) {
+            std::memcpy(row_ptr, rp.data(), sizeof(int64_t) * rp.size());
+            std::memcpy(col, cl.data(), sizeof(int64_t) * cl.size());
+            std::memcpy(val, vl.data(), sizeof(cplx) * vl.size());
+        }
+        return FDA_OK;
+    });
+}
+
 int fda_build(const fda_geometry *g, double k, double eps, const fda_opts *o, fda_plan **out)
 {
     return guarded([&] {
@@ -120,9 +141,10 @@ int fda_matvec(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *
         if (op < FDA_OP_RAW_H || op > FDA_OP_BM_G) throw std::invalid_argument("unknown operator");
         if (in_dev == out_dev) throw std::invalid_argument("input and output must not alias");
         Plan &P = *plan->P;
-        if ((op == FDA_OP_BM_H || op == FDA_OP_BM_G) && !P.has_corr)
-            throw std::invalid_argument("Burton-Miller operators need a plan built with elements");
-        if (op == FDA_OP_BM_G) throw std::runtime_error("corrected G operator not available in this build");
+        if (op == FDA_OP_BM_H && !P.has_corr)
+            throw std::invalid_argument("the corrected H operator needs a plan built with elements");
+        if (op == FDA_OP_BM_G && !P.has_corr_g)
+            throw std::invalid_argument("the corrected G operator needs a plan built with elements and corrections & 2");
         device_matvec(P, op, (const double2 *)in_dev, (double2 *)out_dev, (hipStream_t)stream);
         return FDA_OK;
     });
@@ -136,8 +158,8 @@ int bm_solve(fda_plan *plan, int op, const void *rhs_dev, double tol, int maxit,
         if (!(tol > 0) || maxit < 1 || restart < 1) throw std::invalid_argument("bad solver parameters");
         if (op < FDA_OP_RAW_H || op > FDA_OP_BM_G) throw std::invalid_argument("unknown operator");
         Plan &P = *plan->P;
-        if ((op == FDA_OP_BM_H || op == FDA_OP_BM_G) && !P.has_corr)
-            throw std::invalid_argument("Burton-Miller operators need a plan built with elements");
+        if ((op == FDA_OP_BM_H && !P.has_corr) || (op == FDA_OP_BM_G && !P.has_corr_g))
+            throw std::invalid_argument("corrected operators need a plan built with elements");
         const int rc = device_gmres(P, op, (const double2 *)rhs_dev, tol, maxit, restart, precond, (double2 *)x_dev,
                                     iters_out, relres_out, resid_hist, (hipStream_t)stream);
         if (rc == FDA_NOT_CONVERGED) return fail(rc, "GMRES did not reach the tolerance");

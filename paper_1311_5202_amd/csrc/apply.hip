@@ -483,6 +483,14 @@ void device_upload(Plan &P)
         for (size_t i = 0; i < cv.size(); ++i) cv[i] = make_double2(P.corr_val[i].real(), P.corr_val[i].imag());
         D.corr_val = dupload(D, cv);
     }
+    if (P.has_corr_g) {
+        D.corrg_nnz = (int64_t)P.corrg_col.size();
+        D.corrg_ptr = dupload(D, P.corrg_ptr);
+        D.corrg_col = dupload(D, P.corrg_col);
+        std::vector<double2> cv(P.corrg_val.size());
+        for (size_t i = 0; i < cv.size(); ++i) cv[i] = make_double2(P.corrg_val[i].real(), P.corrg_val[i].imag());
+        D.corrg_val = dupload(D, cv);
+    }
     D.ev.assign((size_t)Device::kRing * 10, nullptr);
     for (auto &e : D.ev) HIP_CHECK(hipEventCreate(&e));
 }
@@ -570,10 +578,13 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
         for (int e = 3; e <= 6; ++e) HIP_CHECK(hipEventRecord(ev[e], st));
     }
     if (tm) HIP_CHECK(hipEventRecord(ev[7], st));
-    hipLaunchKernelGGL(k_permute_out, dim3(nblk(N, 256)), dim3(256), 0, st, D.res, D.perm, in, bm ? 0.5 : 0.0, out, N);
+    hipLaunchKernelGGL(k_permute_out, dim3(nblk(N, 256)), dim3(256), 0, st, D.res, D.perm, in, op == 3 ? 0.5 : 0.0, out, N);
     if (tm) HIP_CHECK(hipEventRecord(ev[8], st));
-    if (bm && D.corr_nnz)
+    if (op == 3 && D.corr_nnz)
         hipLaunchKernelGGL(k_corr, dim3(nblk(N, 256)), dim3(256), 0, st, D.corr_ptr, D.corr_col, D.corr_val, in, out, N);
+    if (op == 4 && D.corrg_nnz)
+        hipLaunchKernelGGL(k_corr, dim3(nblk(N, 256)), dim3(256), 0, st, D.corrg_ptr, D.corrg_col, D.corrg_val, in, out,
+                           N);
     if (tm) {
         HIP_CHECK(hipEventRecord(ev[9], st));
         D.ring_pos++;

@@ -52,6 +52,9 @@ struct Device {
     int64_t corr_nnz = 0;
     int64_t *corr_ptr = nullptr, *corr_col = nullptr;
     double2 *corr_val = nullptr;
+    int64_t corrg_nnz = 0;
+    int64_t *corrg_ptr = nullptr, *corrg_col = nullptr;
+    double2 *corrg_val = nullptr;
     // GMRES work space (allocated on first solve)
     int gm_m = 0;
     double2 *gm_V = nullptr, *gm_w = nullptr, *gm_x = nullptr, *gm_r = nullptr, *gm_h = nullptr;

@@ -137,6 +137,9 @@ struct Plan {
     std::vector<int64_t> corr_col;
     std::vector<cplx> corr_val;
     bool has_corr = false;
+    std::vector<int64_t> corrg_ptr, corrg_col;   // same for the G operator
+    std::vector<cplx> corrg_val;
+    bool has_corr_g = false;
     // statistics
     std::string stats_json;
     double t_setup_tree = 0, t_setup_tmpl = 0, t_setup_ops = 0, t_setup_corr = 0;
@@ -150,6 +153,9 @@ void build_lists(Plan &P);
 void build_templates(Plan &P);
 void build_operators(Plan &P);
 void build_corrections(Plan &P);
+void correction_table_host(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,
+                           double k, int op, std::vector<int64_t> &rp, std::vector<int64_t> &col,
+                           std::vector<cplx> &val);
 void nystrom_nodes(int64_t n_elem, const double *elem, double *pts, double *nrm, double *w);
 void gauss6(double xi[6][2], double wq[6]);
 void p2_shape(double s, double t, double N[6], double dNs[6], double dNt[6]);

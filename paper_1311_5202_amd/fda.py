@@ -24,6 +24,27 @@ def nystrom_nodes(elements: np.ndarray):
     return pts, nrm, w
 
 
+def near_correction(elements, pts, nrm, w, k: float, op: str = "BM_H"):
+    """Host CSR table (row_ptr, col, val) of the locally corrected near field
+    (bem_near_correction), caller node order."""
+    import scipy.sparse as sp
+
+    el = np.ascontiguousarray(elements, dtype=np.float64).reshape(-1, 6, 3)
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    nrm = np.ascontiguousarray(nrm, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    L = _abi.lib()
+    nnz = ctypes.c_int64(0)
+    args = (el.shape[0], el.ctypes.data, pts.ctypes.data, nrm.ctypes.data, w.ctypes.data, float(k), _abi.OPS[op])
+    _abi.check(L.bem_near_correction(*args, ctypes.byref(nnz), None, None, None))
+    n = 6 * el.shape[0]
+    rp = np.empty(n + 1, dtype=np.int64)
+    col = np.empty(nnz.value, dtype=np.int64)
+    val = np.empty(nnz.value, dtype=np.complex128)
+    _abi.check(L.bem_near_correction(*args, ctypes.byref(nnz), rp.ctypes.data, col.ctypes.data, val.ctypes.data))
+    return sp.csr_matrix((val, col, rp), shape=(n, n))
+
+
 def _stream_ptr(stream):
     import torch
 
