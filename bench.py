@@ -87,7 +87,7 @@ def main() -> int:
     plan = fdb.build(pts, nrm, w, k, eps)
     t_build = time.perf_counter() - t0
     st = plan.stats()
-    print(f"[bench] workload={args.workload} N={N} k={k} build {t_build:.1f} s", file=sys.stderr, flush=True)
+    print(f"[bench] workload={args.workload} N={N} k={k} p2p_pairs={st['p2p_pairs']} build {t_build:.1f} s m2l_tile={st.get('m2l_tile')} tiles(t,ch,p,seg)={st.get('m2l_tiles')} lds={st.get('m2l_lds_bytes')}/{st.get('max_lds_per_block')}", file=sys.stderr, flush=True)
     u_host = synth.random_densities(N, 1)
     u = torch.from_numpy(u_host).cuda()
     out = torch.empty_like(u)

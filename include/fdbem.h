@@ -80,6 +80,10 @@ typedef struct {
     int precision;      /* FDA_PREC_FP64 or FDA_PREC_FP32 (far field and P2P in FP32)     */
     int corrections;    /* bit 0: corrected H table, bit 1: corrected G table (needs elements) */
     int verbose;
+    int wedge_factor;   /* directional wedges: cells per cube-face edge = wedge_factor * w / lambda; 0 -> 2 */
+    int m2l_tile;       /* M2L target tile size; 0 -> largest that fits LDS, < 0 -> per-target kernel */
+    double p2p_threshold; /* a far pair whose point counts multiply to at most this is summed
+                             directly instead of translated; 0 -> 1024, < 0 -> never */
 } fda_opts;
 
 typedef struct fda_plan fda_plan;

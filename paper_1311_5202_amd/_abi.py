@@ -32,7 +32,8 @@ class FdaOpts(ctypes.Structure):
     _fields_ = [("svd_eps", ctypes.c_double), ("lowrank_eps", ctypes.c_double), ("leaf_cap", ctypes.c_int),
                 ("leaf_rule", ctypes.c_int), ("c_d", ctypes.c_double), ("far_field", ctypes.c_int),
                 ("lf_grid", ctypes.c_int), ("precision", ctypes.c_int), ("corrections", ctypes.c_int),
-                ("verbose", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("wedge_factor", ctypes.c_int), ("m2l_tile", ctypes.c_int),
+                ("p2p_threshold", ctypes.c_double)]
 
 
 class FdaError(RuntimeError):

@@ -68,6 +68,9 @@ int fda_default_opts(fda_opts *o)
     o->precision = FDA_PREC_FP64;
     o->corrections = 1;
     o->verbose = 0;
+    o->wedge_factor = d.wedge_factor;
+    o->m2l_tile = 0;
+    o->p2p_threshold = 0;
     return FDA_OK;
 }
 
@@ -117,6 +120,9 @@ int fda_build(const fda_geometry *g, double k, double eps, const fda_opts *o, fd
             opt.precision = o->precision;
             opt.corrections = o->corrections;
             opt.verbose = o->verbose;
+            opt.wedge_factor = o->wedge_factor > 0 ? o->wedge_factor : opt.wedge_factor;
+            opt.m2l_tile = o->m2l_tile;
+            if (o->p2p_threshold != 0) opt.p2p_threshold = o->p2p_threshold;
         }
         if (opt.precision != FDA_PREC_FP64) throw std::invalid_argument("precision not available in this build");
         if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");
@@ -190,7 +196,25 @@ int fda_stats(const fda_plan *plan, char *buf, size_t len)
         const Plan &P = *plan->P;
         std::string s = plan_stats(P);
         s.pop_back();  // strip the closing brace to append device figures
-        s += ", \"device_bytes\": " + std::to_string(P.dev ? P.dev->bytes : 0) + ", \"phase_ms\": [";
+        s += ", \"device_bytes\": " + std::to_string(P.dev ? P.dev->bytes : 0);
+        if (P.dev) {
+            int tile = 0, chunk = 0;
+            size_t shm = 0;
+            for (const auto &T : P.dev->m2lt)
+                if (T.n_tiles) tile = T.tile, chunk = T.chunk, shm = std::max(shm, T.shm);
+            int maxsh = 0;
+            (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, P.dev->device);
+            s += ", \"m2l_mode\": " + std::to_string(P.dev->m2l_mode) + ", \"m2l_tile\": " + std::to_string(tile) +
+                 ", \"m2l_chunk\": " + std::to_string(chunk) + ", \"m2l_lds_bytes\": " + std::to_string(shm) +
+                 ", \"max_lds_per_block\": " + std::to_string(maxsh) + ", \"m2l_tiles\": [";
+            for (size_t l = 0; l < P.dev->tile_stats.size(); ++l) {
+                const auto &t = P.dev->tile_stats[l];
+                s += (l ? ", [" : "[") + std::to_string(t[0]) + ", " + std::to_string(t[1]) + ", " + std::to_string(t[2]) +
+                     ", " + std::to_string(t[3]) + "]";
+            }
+            s += "]";
+        }
+        s += ", \"phase_ms\": [";
         for (int t = 0; t < 8; ++t) s += (t ? ", " : "") + std::to_string(P.dev ? P.dev->phase_ms[t] : 0.0);
         s += "]}";
         if (s.size() + 1 > len) throw std::invalid_argument("stats buffer too small");

@@ -126,62 +126,90 @@ __global__ void k_permute_out(const double2 *__restrict__ res, const int64_t *__
     out[j] = v;
 }
 
-// Near field: one 64-lane wavefront per target leaf; sources staged in LDS.
-constexpr int P2P_TILE = 64;
-__global__ __launch_bounds__(P2P_TILE) void k_p2p(const int64_t *__restrict__ ts, const int64_t *__restrict__ te,
-                                                  const int *__restrict__ ptr, const int64_t *__restrict__ ss,
-                                                  const int64_t *__restrict__ se, const double *__restrict__ X,
-                                                  const double *__restrict__ Y, const double *__restrict__ Z,
-                                                  const double *__restrict__ NX, const double *__restrict__ NY,
-                                                  const double *__restrict__ NZ, const double2 *__restrict__ dens,
-                                                  double2 *__restrict__ res, double k, OpC c)
+// Near field.  One 64-lane wavefront per target leaf: lane = (target t,
+// source slice q) with ntp = next power of two >= targets in the leaf and
+// 64/ntp slices, so small leaves still fill the wavefront; the slices are
+// summed with cross-lane shuffles.  The kernel shape is a template parameter
+// so every operator evaluates only its nonzero terms.
+struct PN {
+    double x, y, z, nx, ny, nz, pad0, pad1;
+};
+
+enum { OPK_H = 0, OPK_G = 1, OPK_T1 = 2 };
+
+template <int OPK>
+__device__ __forceinline__ double2 kernel_op(double dx, double dy, double dz, double nxx, double nxy, double nxz,
+                                             double nyx, double nyy, double nyz, double k, double ik)
 {
-    __shared__ double sx[P2P_TILE], sy[P2P_TILE], sz[P2P_TILE], snx[P2P_TILE], sny[P2P_TILE], snz[P2P_TILE];
-    __shared__ double2 sd[P2P_TILE];
-    const int leaf = blockIdx.x;
-    const int tid = threadIdx.x;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
+    double sn, cs;
+    sincos(k * r, &sn, &cs);
+    const double g = ir * kInv4Pi;
+    const double2 G = make_double2(cs * g, sn * g);
+    const double2 a = make_double2(ir, -k);  // 1/r - ik
+    double2 t;
+    if (OPK == OPK_H) {
+        // dG/dn_y + alpha d2G/dn_x dn_y, alpha = i/k
+        const double dnx = (dx * nxx + dy * nxy + dz * nxz) * ir;
+        const double dny = (dx * nyx + dy * nyy + dz * nyz) * ir;
+        const double nn = nxx * nyx + nxy * nyy + nxz * nyz;
+        const double2 q = make_double2(k * k - 3.0 * ir * ir, 3.0 * k * ir);
+        const double p = dnx * dny, f = nn * ir;
+        const double2 B = make_double2(q.x * p + a.x * f, q.y * p + a.y * f);
+        t = make_double2(a.x * dny - B.y * ik, a.y * dny + B.x * ik);
+    } else if (OPK == OPK_G) {
+        // G + alpha dG/dn_x = G [1 - alpha a (d.n_x)/r]
+        const double dnx = (dx * nxx + dy * nxy + dz * nxz) * ir;
+        t = make_double2(1.0 + a.y * dnx * ik, -a.x * dnx * ik);
+    } else {
+        // G + alpha dG/dn_y = G [1 + alpha a (d.n_y)/r]
+        const double dny = (dx * nyx + dy * nyy + dz * nyz) * ir;
+        t = make_double2(1.0 - a.y * dny * ik, a.x * dny * ik);
+    }
+    return cmul(G, t);
+}
+
+template <int OPK>
+__global__ __launch_bounds__(256) void k_p2p(int n_leaf, const int64_t *__restrict__ ts, const int64_t *__restrict__ te,
+                                             const int *__restrict__ ptr, const int64_t *__restrict__ ss,
+                                             const int64_t *__restrict__ se, const PN *__restrict__ pn,
+                                             const double2 *__restrict__ dens, double2 *__restrict__ res, double k)
+{
+    const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (leaf >= n_leaf) return;
+    const int lane = threadIdx.x & 63;
+    const double ik = 1.0 / k;
     const int64_t t0 = ts[leaf], t1 = te[leaf];
     const int e0 = ptr[leaf], e1 = ptr[leaf + 1];
-    for (int64_t ib = t0; ib < t1; ib += P2P_TILE) {
-        const int64_t i = ib + tid;
-        const bool act = i < t1;
-        double xi = 0, yi = 0, zi = 0, nxi = 0, nyi = 0, nzi = 0;
-        if (act) {
-            xi = X[i];
-            yi = Y[i];
-            zi = Z[i];
-            nxi = NX[i];
-            nyi = NY[i];
-            nzi = NZ[i];
-        }
+    for (int64_t ib = t0; ib < t1; ib += 64) {
+        const int nt = (int)min((int64_t)64, t1 - ib);
+        int ntp = 1;
+        while (ntp < nt) ntp <<= 1;
+        const int S = 64 / ntp;
+        const int t = lane & (ntp - 1), q = lane / ntp;
+        const bool act = t < nt;
+        const int64_t i = ib + (act ? t : 0);
+        const PN X = pn[i];
         double2 acc = make_double2(0.0, 0.0);
-        for (int e = e0; e < e1; ++e) {
-            const int64_t s0 = ss[e], s1 = se[e];
-            for (int64_t jb = s0; jb < s1; jb += P2P_TILE) {
-                __syncthreads();
-                const int64_t j = jb + tid;
-                if (j < s1) {
-                    sx[tid] = X[j];
-                    sy[tid] = Y[j];
-                    sz[tid] = Z[j];
-                    snx[tid] = NX[j];
-                    sny[tid] = NY[j];
-                    snz[tid] = NZ[j];
-                    sd[tid] = dens[j];
-                }
-                __syncthreads();
-                const int cnt = (int)((s1 - jb) < P2P_TILE ? (s1 - jb) : P2P_TILE);
-                if (act) {
-                    for (int q = 0; q < cnt; ++q) {
-                        if (jb + q == i) continue;
-                        const double2 K = kernel_full(xi - sx[q], yi - sy[q], zi - sz[q], nxi, nyi, nzi, snx[q],
-                                                      sny[q], snz[q], k, c);
-                        acc = cadd(acc, cmul(K, sd[q]));
-                    }
+        if (act) {
+            for (int e = e0; e < e1; ++e) {
+                const int64_t s1 = se[e];
+                for (int64_t j = ss[e] + q; j < s1; j += S) {
+                    if (j == i) continue;
+                    const PN Y = pn[j];
+                    const double2 K = kernel_op<OPK>(X.x - Y.x, X.y - Y.y, X.z - Y.z, X.nx, X.ny, X.nz, Y.nx, Y.ny,
+                                                     Y.nz, k, ik);
+                    acc = cadd(acc, cmul(K, dens[j]));
                 }
             }
         }
-        if (act) res[i] = acc;
+        for (int off = ntp; off < 64; off <<= 1) {
+            acc.x += __shfl_xor(acc.x, off);
+            acc.y += __shfl_xor(acc.y, off);
+        }
+        if (act && q == 0) res[ib + t] = acc;
     }
 }
 
@@ -321,6 +349,219 @@ __global__ __launch_bounds__(GEMV_BLOCK) void k_gemv(const int64_t *__restrict__
     if (i1 < rows) out[ob + i1] = cadd(out[ob + i1], acc1);
 }
 
+
+// M2L over target tiles (see M2LTiles): per chunk the operator is read once
+// per row and applied to up to four pairs held in registers; targets
+// accumulate in LDS and are written once at the end (no atomics).
+// LDS: Y[tile][s] | X[chunk][s] | T[chunk][rmax].
+constexpr int M2L_BLOCK = 256;
+__global__ __launch_bounds__(M2L_BLOCK) void k_m2l_tile(int s, int rmax, int tile, int chunk, int nseg,
+                                                        double2 *__restrict__ part,
+                                                        const int64_t *__restrict__ tgt_off,
+                                                        const int *__restrict__ tile_ntgt,
+                                                        const int *__restrict__ tile_cptr,
+                                                        const int64_t *__restrict__ ch_mat,
+                                                        const int *__restrict__ ch_rank,
+                                                        const int *__restrict__ ch_pptr, const int *__restrict__ pr_tl,
+                                                        const int64_t *__restrict__ pr_src,
+                                                        const double2 *__restrict__ mat,
+                                                        const double2 *__restrict__ od, double2 *__restrict__ id)
+{
+    extern __shared__ double2 sh[];
+    double2 *Y = sh;
+    double2 *X = Y + (size_t)tile * s;
+    double2 *Tb = X + (size_t)chunk * s;
+    const int q = blockIdx.x / nseg, z = blockIdx.x - q * nseg, tid = threadIdx.x;
+    const int nt = tile_ntgt[q];
+    for (int i = tid; i < nt * s; i += M2L_BLOCK) Y[i] = make_double2(0.0, 0.0);
+    // this workgroup's share of the tile's chunks
+    const int cb = tile_cptr[q], ce = tile_cptr[q + 1];
+    const int c0 = cb + (int)((int64_t)(ce - cb) * z / nseg), c1 = cb + (int)((int64_t)(ce - cb) * (z + 1) / nseg);
+    for (int c = c0; c < c1; ++c) {
+        const int p0 = ch_pptr[c], n = ch_pptr[c + 1] - p0;
+        __syncthreads();
+        for (int i = tid; i < n * s; i += M2L_BLOCK) {
+            const int p = i / s, j = i - p * s;
+            X[i] = od[pr_src[p0 + p] + j];
+        }
+        __syncthreads();
+        const double2 *M = mat + ch_mat[c];
+        const int r = ch_rank[c];
+        const int G = (n + 3) >> 2;
+        if (r < 0) {
+            for (int i = tid; i < G * s; i += M2L_BLOCK) {
+                const int g = i / s, row = i - g * s;
+                double2 a0 = make_double2(0, 0), a1 = a0, a2 = a0, a3 = a0;
+                const double2 *x0 = X + (size_t)(4 * g) * s;
+                const int np = min(4, n - 4 * g);
+                for (int j = 0; j < s; ++j) {
+                    const double2 m = M[row + (size_t)j * s];
+                    a0 = cadd(a0, cmul(m, x0[j]));
+                    if (np > 1) a1 = cadd(a1, cmul(m, x0[s + j]));
+                    if (np > 2) a2 = cadd(a2, cmul(m, x0[2 * s + j]));
+                    if (np > 3) a3 = cadd(a3, cmul(m, x0[3 * s + j]));
+                }
+                const int *tl = pr_tl + p0 + 4 * g;
+                Y[tl[0] * s + row] = cadd(Y[tl[0] * s + row], a0);
+                if (np > 1) Y[tl[1] * s + row] = cadd(Y[tl[1] * s + row], a1);
+                if (np > 2) Y[tl[2] * s + row] = cadd(Y[tl[2] * s + row], a2);
+                if (np > 3) Y[tl[3] * s + row] = cadd(Y[tl[3] * s + row], a3);
+            }
+        } else {
+            const double2 *U = M, *V = M + (size_t)s * r;
+            for (int i = tid; i < G * r; i += M2L_BLOCK) {
+                const int g = i / r, qq = i - g * r;
+                double2 a0 = make_double2(0, 0), a1 = a0, a2 = a0, a3 = a0;
+                const double2 *x0 = X + (size_t)(4 * g) * s;
+                const int np = min(4, n - 4 * g);
+                for (int j = 0; j < s; ++j) {
+                    const double2 m = V[qq + (size_t)j * r];
+                    a0 = cadd(a0, cmul(m, x0[j]));
+                    if (np > 1) a1 = cadd(a1, cmul(m, x0[s + j]));
+                    if (np > 2) a2 = cadd(a2, cmul(m, x0[2 * s + j]));
+                    if (np > 3) a3 = cadd(a3, cmul(m, x0[3 * s + j]));
+                }
+                double2 *t0 = Tb + (size_t)(4 * g) * rmax + qq;
+                t0[0] = a0;
+                if (np > 1) t0[rmax] = a1;
+                if (np > 2) t0[2 * rmax] = a2;
+                if (np > 3) t0[3 * rmax] = a3;
+            }
+            __syncthreads();
+            for (int i = tid; i < G * s; i += M2L_BLOCK) {
+                const int g = i / s, row = i - g * s;
+                double2 a0 = make_double2(0, 0), a1 = a0, a2 = a0, a3 = a0;
+                const double2 *t0 = Tb + (size_t)(4 * g) * rmax;
+                const int np = min(4, n - 4 * g);
+                for (int qq = 0; qq < r; ++qq) {
+                    const double2 m = U[row + (size_t)qq * s];
+                    a0 = cadd(a0, cmul(m, t0[qq]));
+                    if (np > 1) a1 = cadd(a1, cmul(m, t0[rmax + qq]));
+                    if (np > 2) a2 = cadd(a2, cmul(m, t0[2 * rmax + qq]));
+                    if (np > 3) a3 = cadd(a3, cmul(m, t0[3 * rmax + qq]));
+                }
+                const int *tl = pr_tl + p0 + 4 * g;
+                Y[tl[0] * s + row] = cadd(Y[tl[0] * s + row], a0);
+                if (np > 1) Y[tl[1] * s + row] = cadd(Y[tl[1] * s + row], a1);
+                if (np > 2) Y[tl[2] * s + row] = cadd(Y[tl[2] * s + row], a2);
+                if (np > 3) Y[tl[3] * s + row] = cadd(Y[tl[3] * s + row], a3);
+            }
+        }
+    }
+    __syncthreads();
+    if (nseg == 1) {
+        for (int i = tid; i < nt * s; i += M2L_BLOCK) {
+            const int t = i / s, row = i - t * s;
+            double2 *o = id + tgt_off[(size_t)q * tile + t] + row;
+            *o = cadd(*o, Y[i]);
+        }
+    } else {
+        // partial sums, reduced in a fixed order by k_m2l_reduce
+        double2 *pq = part + ((size_t)q * nseg + z) * (size_t)tile * s;
+        for (int i = tid; i < nt * s; i += M2L_BLOCK) pq[i] = Y[i];
+    }
+}
+
+__global__ void k_m2l_reduce(int s, int tile, int nseg, const double2 *__restrict__ part,
+                             const int64_t *__restrict__ tgt_off, const int *__restrict__ tile_ntgt,
+                             double2 *__restrict__ id)
+{
+    const int q = blockIdx.x;
+    const int nt = tile_ntgt[q];
+    for (int i = threadIdx.x; i < nt * s; i += blockDim.x) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int z = 0; z < nseg; ++z) acc = cadd(acc, part[((size_t)q * nseg + z) * (size_t)tile * s + i]);
+        const int t = i / s, row = i - t * s;
+        double2 *o = id + tgt_off[(size_t)q * tile + t] + row;
+        *o = cadd(*o, acc);
+    }
+}
+
+
+// M2L by operator chunks: one wavefront per chunk of <= M2LC_CH pairs sharing
+// one operator.  Lane = output row; each lane keeps the chunk's pairs in
+// registers so every operator element read from cache feeds M2LC_CH complex
+// FMAs; sources are staged per wavefront in LDS; results go to the targets
+// with FP64 atomic adds (hardware global_atomic_add_f64).
+constexpr int M2LC_CH = 8;
+constexpr int M2LC_WAVES = 4;
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * M2LC_WAVES) void k_m2l_chunks(int n_chunks, int s, int rmax,
+                                                                const int64_t *__restrict__ ch_mat,
+                                                                const int *__restrict__ ch_rank,
+                                                                const int *__restrict__ ch_pptr,
+                                                                const int64_t *__restrict__ pr_tgt,
+                                                                const int64_t *__restrict__ pr_src,
+                                                                const double2 *__restrict__ mat,
+                                                                const double2 *__restrict__ od, double2 *id)
+{
+    extern __shared__ double2 sh[];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * M2LC_WAVES + wv;
+    if (c >= n_chunks) return;
+    double2 *X = sh + (size_t)wv * (M2LC_CH * s + M2LC_CH * rmax);
+    double2 *T = X + M2LC_CH * s;
+    const int p0 = ch_pptr[c], n = ch_pptr[c + 1] - p0;
+    for (int i = lane; i < n * s; i += 64) {
+        const int p = i / s, j = i - p * s;
+        X[p * s + j] = od[pr_src[p0 + p] + j];
+    }
+    wave_sync();
+    const double2 *M = mat + ch_mat[c];
+    const int r = ch_rank[c];
+    double2 acc[M2LC_CH];
+    if (r >= 0) {
+        const double2 *V = M + (size_t)s * r;
+        for (int qq = lane; qq < r; qq += 64) {
+#pragma unroll
+            for (int p = 0; p < M2LC_CH; ++p) acc[p] = make_double2(0.0, 0.0);
+            for (int j = 0; j < s; ++j) {
+                const double2 m = V[qq + (size_t)j * r];
+#pragma unroll
+                for (int p = 0; p < M2LC_CH; ++p)
+                    if (p < n) acc[p] = cadd(acc[p], cmul(m, X[p * s + j]));
+            }
+#pragma unroll
+            for (int p = 0; p < M2LC_CH; ++p)
+                if (p < n) T[p * rmax + qq] = acc[p];
+        }
+        wave_sync();
+    }
+    for (int row = lane; row < s; row += 64) {
+#pragma unroll
+        for (int p = 0; p < M2LC_CH; ++p) acc[p] = make_double2(0.0, 0.0);
+        if (r < 0) {
+            for (int j = 0; j < s; ++j) {
+                const double2 m = M[row + (size_t)j * s];
+#pragma unroll
+                for (int p = 0; p < M2LC_CH; ++p)
+                    if (p < n) acc[p] = cadd(acc[p], cmul(m, X[p * s + j]));
+            }
+        } else {
+            for (int qq = 0; qq < r; ++qq) {
+                const double2 m = M[row + (size_t)qq * s];
+#pragma unroll
+                for (int p = 0; p < M2LC_CH; ++p)
+                    if (p < n) acc[p] = cadd(acc[p], cmul(m, T[p * rmax + qq]));
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < M2LC_CH; ++p)
+            if (p < n) {
+                double *o = (double *)(id + pr_tgt[p0 + p] + row);
+                atomicAdd(o, acc[p].x);
+                atomicAdd(o + 1, acc[p].y);
+            }
+    }
+}
+
 // Near-field correction, caller order: out_i += sum_c val_c in_{col_c}.
 __global__ void k_corr(const int64_t *__restrict__ rp, const int64_t *__restrict__ col,
                        const double2 *__restrict__ val, const double2 *__restrict__ in, double2 *__restrict__ out,
@@ -387,6 +628,43 @@ static DGemv upload_gemv(Device &D, const GemvList &G)
     return g;
 }
 
+static DTiles upload_tiles(Device &D, const M2LTiles &T)
+{
+    DTiles d;
+    d.n_tiles = (int)T.tile_ntgt.size();
+    d.s = T.s;
+    d.rmax = std::max(1, T.max_rank);
+    d.tile = T.tile;
+    d.chunk = T.chunk;
+    if (d.n_tiles == 0) return d;
+    d.shm = sizeof(double2) * ((size_t)(d.tile + d.chunk) * d.s + (size_t)d.chunk * d.rmax);
+    d.tgt_off = dupload(D, T.tgt_off);
+    d.tile_ntgt = dupload(D, T.tile_ntgt);
+    d.tile_cptr = dupload(D, T.tile_cptr);
+    d.ch_mat = dupload(D, T.ch_mat);
+    d.ch_rank = dupload(D, T.ch_rank);
+    d.ch_pptr = dupload(D, T.ch_pptr);
+    d.pr_tl = dupload(D, T.pr_tl);
+    d.pr_src = dupload(D, T.pr_src);
+    return d;
+}
+
+static DChunks upload_chunks(Device &D, const M2LChunks &C)
+{
+    DChunks d;
+    d.n = (int)C.ch_mat.size();
+    d.s = C.s;
+    d.rmax = std::max(1, C.max_rank);
+    if (d.n == 0) return d;
+    d.shm = sizeof(double2) * (size_t)M2LC_WAVES * (M2LC_CH * d.s + M2LC_CH * d.rmax);
+    d.ch_mat = dupload(D, C.ch_mat);
+    d.ch_rank = dupload(D, C.ch_rank);
+    d.ch_pptr = dupload(D, C.ch_pptr);
+    d.pr_tgt = dupload(D, C.pr_tgt);
+    d.pr_src = dupload(D, C.pr_src);
+    return d;
+}
+
 static DLeaf upload_leaf(Device &D, const Plan &P, const std::vector<LeafTask> &T)
 {
     DLeaf L;
@@ -426,6 +704,12 @@ void device_upload(Plan &P)
     D.nz = dupload(D, P.pnz);
     D.w = dupload(D, P.pw);
     D.perm = dupload(D, P.perm);
+    {
+        std::vector<PN> pnh(P.N);
+        for (int64_t i = 0; i < P.N; ++i)
+            pnh[i] = PN{P.px[i], P.py[i], P.pz[i], P.pnx[i], P.pny[i], P.pnz[i], 0.0, 0.0};
+        D.pn = (void *)dupload(D, pnh);
+    }
     D.n_leaf = (int)P.leaves.size();
     D.p2p_ts = dupload(D, P.p2p_tgt_start);
     D.p2p_te = dupload(D, P.p2p_tgt_end);
@@ -465,6 +749,83 @@ void device_upload(Plan &P)
             D.m2m[l] = upload_gemv(D, P.m2m_lists[l]);
             D.m2l[l] = upload_gemv(D, P.m2l_lists[l]);
             D.l2l[l] = upload_gemv(D, P.l2l_lists[l]);
+        }
+        int maxsh = 65536;
+        (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, D.device);
+        // M2L mode: 0 operator chunks with atomics (default), 1 per-target GEMV,
+        // 2 deterministic target tiles
+        D.m2l_mode = P.opt.m2l_tile < 0 ? 1 : P.opt.m2l_tile > 0 ? 2 : 0;
+        if (D.m2l_mode == 0) {
+            build_m2l_chunks(P, M2LC_CH);
+            D.m2lc.resize(nlev);
+            for (int l = 0; l < nlev; ++l) {
+                D.m2lc[l] = upload_chunks(D, P.m2l_chunks[l]);
+                D.tile_stats.push_back({0, (int64_t)P.m2l_chunks[l].ch_mat.size(),
+                                        (int64_t)P.m2l_chunks[l].pr_tgt.size(), 0});
+                if (D.m2lc[l].shm > (size_t)maxsh) D.m2l_mode = 1;
+                if (D.m2lc[l].shm > 65536)
+                    HIP_CHECK(hipFuncSetAttribute((const void *)k_m2l_chunks,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)D.m2lc[l].shm));
+            }
+            P.m2l_chunks.clear();
+        }
+        if (D.m2l_mode == 2) {
+            // deterministic tiles: the largest tile whose LDS footprint fits one workgroup
+            int tile = P.opt.m2l_tile, chunk = std::min(32, tile);
+            auto fits = [&](int t, int c) {
+                for (int l = 0; l < nlev; ++l) {
+                    const GemvList &G = P.m2l_lists[l];
+                    if (G.out_off.empty()) continue;
+                    int rmax = 1;
+                    for (int r : G.rank) rmax = std::max(rmax, r);
+                    if (sizeof(double2) * ((size_t)(t + c) * G.rows + (size_t)c * rmax) > (size_t)maxsh) return false;
+                }
+                return true;
+            };
+            while (tile > 4 && !fits(tile, chunk)) {
+                tile /= 2;
+                chunk = std::min(chunk, tile);
+            }
+            if (!fits(tile, chunk)) D.m2l_mode = 1;
+        }
+        if (D.m2l_mode == 2) {
+            int tile = P.opt.m2l_tile, chunk = std::min(32, tile);
+            auto fits = [&](int t, int c) {
+                for (int l = 0; l < nlev; ++l) {
+                    const GemvList &G = P.m2l_lists[l];
+                    if (G.out_off.empty()) continue;
+                    int rmax = 1;
+                    for (int r : G.rank) rmax = std::max(rmax, r);
+                    if (sizeof(double2) * ((size_t)(t + c) * G.rows + (size_t)c * rmax) > (size_t)maxsh) return false;
+                }
+                return true;
+            };
+            while (tile > 4 && !fits(tile, chunk)) {
+                tile /= 2;
+                chunk = std::min(chunk, tile);
+            }
+            build_m2l_tiles(P, tile, chunk);
+            D.m2lt.resize(nlev);
+            int cus = 256;
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, D.device);
+            size_t part = 0;
+            for (int l = 0; l < nlev; ++l) {
+                D.m2lt[l] = upload_tiles(D, P.m2l_tiles[l]);
+                DTiles &T = D.m2lt[l];
+                D.tile_stats.push_back({(int64_t)P.m2l_tiles[l].tile_ntgt.size(), (int64_t)P.m2l_tiles[l].ch_mat.size(),
+                                        (int64_t)P.m2l_tiles[l].pr_tl.size(), 0});
+                if (T.n_tiles) {
+                    // enough workgroups to fill the chip: split tiles into segments
+                    T.nseg = std::max(1, std::min(16, (8 * cus + T.n_tiles - 1) / T.n_tiles));
+                    if (T.nseg > 1) part = std::max(part, (size_t)T.n_tiles * T.nseg * T.tile * T.s);
+                }
+                D.tile_stats.back()[3] = T.nseg;
+                if (D.m2lt[l].shm > 65536)
+                    HIP_CHECK(hipFuncSetAttribute((const void *)k_m2l_tile,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)D.m2lt[l].shm));
+            }
+            P.m2l_tiles.clear();
+            if (part) D.m2l_part = dalloc<double2>(D, part);
         }
         D.s2m = upload_leaf(D, P, P.s2m_tasks);
         D.l2t = upload_leaf(D, P, P.l2t_tasks);
@@ -552,8 +913,19 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
     if (tm) HIP_CHECK(hipEventRecord(ev[0], st));
     hipLaunchKernelGGL(k_permute_in, dim3(nblk(N, 256)), dim3(256), 0, st, in, D.perm, D.w, D.dens, N);
     if (tm) HIP_CHECK(hipEventRecord(ev[1], st));
-    hipLaunchKernelGGL(k_p2p, dim3(D.n_leaf), dim3(P2P_TILE), 0, st, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
-                       D.x, D.y, D.z, D.nx, D.ny, D.nz, D.dens, D.res, P.k, c);
+    {
+        const int opk = (op == 0 || op == 3) ? OPK_H : (op == 1 || op == 4) ? OPK_G : OPK_T1;
+        const dim3 g((D.n_leaf + 3) / 4), b(256);
+        if (opk == OPK_H)
+            hipLaunchKernelGGL(k_p2p<OPK_H>, g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
+                               (const PN *)D.pn, D.dens, D.res, P.k);
+        else if (opk == OPK_G)
+            hipLaunchKernelGGL(k_p2p<OPK_G>, g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
+                               (const PN *)D.pn, D.dens, D.res, P.k);
+        else
+            hipLaunchKernelGGL(k_p2p<OPK_T1>, g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
+                               (const PN *)D.pn, D.dens, D.res, P.k);
+    }
     if (tm) HIP_CHECK(hipEventRecord(ev[2], st));
     if (P.opt.far_field) {
         if (D.n_od) hipLaunchKernelGGL(k_fill_zero, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, D.od, D.n_od);
@@ -566,7 +938,26 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
         if (tm) HIP_CHECK(hipEventRecord(ev[3], st));
         for (int l = D.n_lev - 2; l >= 0; --l) run_gemv<TAG_M2M>(D.m2m[l], D.mat, D.od, D.od, st);
         if (tm) HIP_CHECK(hipEventRecord(ev[4], st));
-        for (int l = 0; l < D.n_lev; ++l) run_gemv<TAG_M2L>(D.m2l[l], D.mat, D.od, D.id, st);
+        for (int l = 0; l < D.n_lev; ++l) {
+            if (D.m2l_mode == 0) {
+                const DChunks &C = D.m2lc[l];
+                if (C.n)
+                    hipLaunchKernelGGL(k_m2l_chunks, dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES), dim3(64 * M2LC_WAVES),
+                                       C.shm, st, C.n, C.s, C.rmax, C.ch_mat, C.ch_rank, C.ch_pptr, C.pr_tgt,
+                                       C.pr_src, D.mat, D.od, D.id);
+            } else if (D.m2l_mode == 2) {
+                const DTiles &T = D.m2lt[l];
+                if (T.n_tiles) {
+                    hipLaunchKernelGGL(k_m2l_tile, dim3(T.n_tiles * T.nseg), dim3(M2L_BLOCK), T.shm, st, T.s, T.rmax,
+                                       T.tile, T.chunk, T.nseg, D.m2l_part, T.tgt_off, T.tile_ntgt, T.tile_cptr,
+                                       T.ch_mat, T.ch_rank, T.ch_pptr, T.pr_tl, T.pr_src, D.mat, D.od, D.id);
+                    if (T.nseg > 1)
+                        hipLaunchKernelGGL(k_m2l_reduce, dim3(T.n_tiles), dim3(256), 0, st, T.s, T.tile, T.nseg,
+                                           D.m2l_part, T.tgt_off, T.tile_ntgt, D.id);
+                }
+            } else
+                run_gemv<TAG_M2L>(D.m2l[l], D.mat, D.od, D.id, st);
+        }
         if (tm) HIP_CHECK(hipEventRecord(ev[5], st));
         for (int l = 1; l < D.n_lev; ++l) run_gemv<TAG_L2L>(D.l2l[l], D.mat, D.id, D.id, st);
         if (tm) HIP_CHECK(hipEventRecord(ev[6], st));

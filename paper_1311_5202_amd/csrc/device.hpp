@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
+
 #include "plan.hpp"
 
 namespace fdbem {
@@ -17,6 +19,20 @@ struct DGemv {
     int *rank = nullptr;
 };
 
+struct DTiles {
+    int n_tiles = 0, s = 0, rmax = 1, tile = 0, chunk = 0, nseg = 1;
+    size_t shm = 0;
+    int64_t *tgt_off = nullptr, *ch_mat = nullptr, *pr_src = nullptr;
+    int *tile_ntgt = nullptr, *tile_cptr = nullptr, *ch_rank = nullptr, *ch_pptr = nullptr, *pr_tl = nullptr;
+};
+
+struct DChunks {
+    int n = 0, s = 0, rmax = 1;
+    size_t shm = 0;
+    int64_t *ch_mat = nullptr, *pr_tgt = nullptr, *pr_src = nullptr;
+    int *ch_rank = nullptr, *ch_pptr = nullptr;
+};
+
 struct DLeaf {
     int n = 0;
     int64_t *start = nullptr, *end = nullptr, *slot = nullptr;
@@ -29,6 +45,7 @@ struct Device {
     // points (sorted order)
     double *x = nullptr, *y = nullptr, *z = nullptr, *nx = nullptr, *ny = nullptr, *nz = nullptr, *w = nullptr;
     int64_t *perm = nullptr;
+    void *pn = nullptr;          // packed positions and normals (64 B per point)
     // near field
     int n_leaf = 0;
     int64_t *p2p_ts = nullptr, *p2p_te = nullptr, *p2p_ss = nullptr, *p2p_se = nullptr;
@@ -42,6 +59,11 @@ struct Device {
     // translations
     double2 *mat = nullptr;
     std::vector<DGemv> m2m, m2l, l2l;  // per level
+    std::vector<DTiles> m2lt;          // per level, tiled M2L
+    std::vector<DChunks> m2lc;         // per level, operator-chunk M2L
+    int m2l_mode = 0;                  // 0 operator chunks, 1 per-target GEMV, 2 target tiles
+    double2 *m2l_part = nullptr;       // partial sums of split tiles
+    std::vector<std::array<int64_t, 4>> tile_stats;  // per level: tiles, chunks, pairs, segments
     DLeaf s2m, l2t;
     // work vectors
     double2 *dens = nullptr;     // weighted sorted density (N)

@@ -20,6 +20,9 @@ struct Options {
     double lowrank_eps = 0;  // truncation of the M2L low-rank factors (0 -> eps)
     int leaf_cap = 64;       // max points per leaf
     int leaf_rule = 0;       // 0: leaves are low-frequency cubes (w < lambda)
+    int wedge_factor = 2;    // wedge cells per face edge = wedge_factor * w / lambda
+    int m2l_tile = 0;        // M2L target tile (0 auto, <0 per-target GEMV kernel)
+    double p2p_threshold = 1024;  // far pairs with n_B * n_C <= this are summed directly
     double c_d = 1.0 / M_PI; // high-frequency near-field constant
     int far_field = 1;       // 0: every pair by direct summation (debug / tiny problems)
     int lf_grid = 0;         // points per edge of the low-frequency surface grids (0 -> auto)
@@ -91,6 +94,33 @@ struct GemvList {
     std::vector<int> rank;           // per entry: -1 dense, else low-rank r (U then V stored)
     int rows = 0, cols = 0;          // output / input dimension
     int trans = 0;                   // 1: use Mat^T (L2L)
+    std::vector<int> out_wedge;      // per output slot: its wedge (M2L tiling order)
+};
+
+// M2L in target tiles: every tile owns up to `tile` target slots of one level
+// (same wedge, consecutive cubes in octree order); its pairs are grouped into chunks that share one operator and hit
+// distinct targets, so a workgroup reuses each operator across the chunk and
+// accumulates its targets in LDS without atomics.
+struct M2LTiles {
+    int tile = 0, chunk = 0, s = 0, max_rank = 0;
+    std::vector<int64_t> tgt_off;    // per target slot (tile q owns entries q*tile ..): density offset
+    std::vector<int> tile_ntgt;      // per tile: number of target slots
+    std::vector<int> tile_cptr;      // per tile: chunk range (size n_tiles+1)
+    std::vector<int64_t> ch_mat;     // per chunk: operator offset in the pool
+    std::vector<int> ch_rank;        // per chunk: -1 dense, else low-rank r
+    std::vector<int> ch_pptr;        // per chunk: pair range (size n_chunks+1)
+    std::vector<int> pr_tl;          // per pair: target index within the tile
+    std::vector<int64_t> pr_src;     // per pair: source density offset
+};
+
+// M2L by operator: pairs sharing one compressed operator are cut into chunks
+// of at most `chunk` pairs; one wavefront applies the operator to a chunk and
+// adds the results to the targets with FP64 atomics.
+struct M2LChunks {
+    int chunk = 0, s = 0, max_rank = 0;
+    std::vector<int64_t> ch_mat;
+    std::vector<int> ch_rank, ch_pptr;
+    std::vector<int64_t> pr_tgt, pr_src;
 };
 
 struct LeafTask {
@@ -129,6 +159,8 @@ struct Plan {
     std::vector<std::vector<std::array<int, 4>>> m2l_keyinfo;  // per level, per key: (orbit or -1, offset)
     std::vector<cplx> matpool;                   // all translation matrices
     std::vector<GemvList> m2m_lists, m2l_lists, l2l_lists;  // per level (parent / pair / child level)
+    std::vector<M2LTiles> m2l_tiles;                        // per level
+    std::vector<M2LChunks> m2l_chunks;                      // per level
     std::vector<LeafTask> s2m_tasks, l2t_tasks;
     int64_t out_total = 0, in_total = 0;         // density array sizes
     int max_s = 0, max_Y = 0, max_Y_leaf = 0;
@@ -153,6 +185,8 @@ void build_lists(Plan &P);
 void build_templates(Plan &P);
 void build_operators(Plan &P);
 void build_corrections(Plan &P);
+void build_m2l_tiles(Plan &P, int tile, int chunk);
+void build_m2l_chunks(Plan &P, int chunk);
 void correction_table_host(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,
                            double k, int op, std::vector<int64_t> &rp, std::vector<int64_t> &col,
                            std::vector<cplx> &val);

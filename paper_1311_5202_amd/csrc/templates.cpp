@@ -294,12 +294,16 @@ void build_operators(Plan &P)
         }
         GemvList &G = P.m2l_lists[l];
         G.rows = G.cols = s;
+        std::vector<int> slot_wedge(L.n_in, 0);
+        for (size_t t = 0; t < L.in_slot.size(); ++t)
+            if (L.in_slot[t] >= 0) slot_wedge[L.in_slot[t]] = (int)(t % L.nwedge);
         G.ptr.push_back(0);
         const auto &V = P.m2l[l];
         for (size_t q = 0; q < V.size(); ++q) {
             if (q == 0 || V[q].tgt_slot != V[q - 1].tgt_slot) {
                 if (q > 0) G.ptr.push_back((int)G.in_off.size());
                 G.out_off.push_back(L.in_base + (int64_t)V[q].tgt_slot * s);
+                G.out_wedge.push_back(slot_wedge[V[q].tgt_slot]);
             }
             G.in_off.push_back(L.out_base + (int64_t)V[q].src_slot * s);
             G.mat_off.push_back(key_off[V[q].key]);
@@ -447,6 +451,118 @@ void build_operators(Plan &P)
             P.l2t_tasks.push_back(t);
         }
         if (so >= 0 || si >= 0) P.max_Y_leaf = std::max(P.max_Y_leaf, (int)P.tmpl[c.level].Y.size() / 3);
+    }
+}
+
+}  // namespace fdbem
+
+namespace fdbem {
+
+void build_m2l_tiles(Plan &P, int tile, int chunk)
+{
+    const int nlev = (int)P.levels.size();
+    P.m2l_tiles.assign(nlev, M2LTiles());
+    for (int l = 0; l < nlev; ++l) {
+        const GemvList &G = P.m2l_lists[l];
+        M2LTiles &T = P.m2l_tiles[l];
+        T.tile = tile;
+        T.chunk = chunk;
+        T.s = G.rows;
+        const int n_out = (int)G.out_off.size();
+        if (n_out == 0) continue;
+        std::vector<int> order(n_out);
+        for (int t = 0; t < n_out; ++t) order[t] = t;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return G.out_wedge[a] < G.out_wedge[b]; });
+        T.tgt_off.resize(n_out);
+        for (int t = 0; t < n_out; ++t) T.tgt_off[t] = G.out_off[order[t]];
+        struct E {
+            int64_t mat;
+            int rank, tl;
+            int64_t src;
+        };
+        std::vector<E> es, rest;
+        std::vector<char> used(tile, 0);
+        for (int t0 = 0; t0 < n_out; t0 += tile) {
+            const int nt = std::min(tile, n_out - t0);
+            es.clear();
+            for (int t = 0; t < nt; ++t)
+                for (int e = G.ptr[order[t0 + t]]; e < G.ptr[order[t0 + t] + 1]; ++e)
+                    es.push_back({G.mat_off[e], G.rank[e], t, G.in_off[e]});
+            // group by operator; runs split into chunks with distinct targets
+            std::stable_sort(es.begin(), es.end(), [](const E &a, const E &b) { return a.mat < b.mat; });
+            T.tile_ntgt.push_back(nt);
+            T.tile_cptr.push_back((int)T.ch_mat.size());
+            size_t i = 0;
+            while (i < es.size()) {
+                size_t j = i;
+                while (j < es.size() && es[j].mat == es[i].mat) ++j;
+                std::vector<E> pending(es.begin() + i, es.begin() + j);
+                while (!pending.empty()) {
+                    rest.clear();
+                    std::fill(used.begin(), used.end(), 0);
+                    int cnt = 0;
+                    T.ch_mat.push_back(pending[0].mat);
+                    T.ch_rank.push_back(pending[0].rank);
+                    T.ch_pptr.push_back((int)T.pr_tl.size());
+                    for (const E &x : pending) {
+                        if (cnt < chunk && !used[x.tl]) {
+                            used[x.tl] = 1;
+                            T.pr_tl.push_back(x.tl);
+                            T.pr_src.push_back(x.src);
+                            ++cnt;
+                        } else
+                            rest.push_back(x);
+                    }
+                    pending.swap(rest);
+                }
+                i = j;
+            }
+        }
+        T.tile_cptr.push_back((int)T.ch_mat.size());
+        T.ch_pptr.push_back((int)T.pr_tl.size());
+        for (int r : T.ch_rank) T.max_rank = std::max(T.max_rank, r);
+    }
+}
+
+}  // namespace fdbem
+
+namespace fdbem {
+
+void build_m2l_chunks(Plan &P, int chunk)
+{
+    const int nlev = (int)P.levels.size();
+    P.m2l_chunks.assign(nlev, M2LChunks());
+    for (int l = 0; l < nlev; ++l) {
+        const GemvList &G = P.m2l_lists[l];
+        M2LChunks &C = P.m2l_chunks[l];
+        C.chunk = chunk;
+        C.s = G.rows;
+        const int n_out = (int)G.out_off.size();
+        if (n_out == 0) continue;
+        const int64_t ne = (int64_t)G.in_off.size();
+        std::vector<int64_t> tgt(ne);
+        for (int o = 0; o < n_out; ++o)
+            for (int e = G.ptr[o]; e < G.ptr[o + 1]; ++e) tgt[e] = G.out_off[o];
+        std::vector<int64_t> idx(ne);
+        for (int64_t e = 0; e < ne; ++e) idx[e] = e;
+        // by operator, then by target (nearby targets share cache lines)
+        std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+            return G.mat_off[a] != G.mat_off[b] ? G.mat_off[a] < G.mat_off[b] : tgt[a] < tgt[b];
+        });
+        C.pr_tgt.resize(ne);
+        C.pr_src.resize(ne);
+        for (int64_t q = 0; q < ne; ++q) {
+            const int64_t e = idx[q];
+            if (q == 0 || G.mat_off[e] != G.mat_off[idx[q - 1]] || (q - C.ch_pptr.back()) >= chunk) {
+                C.ch_mat.push_back(G.mat_off[e]);
+                C.ch_rank.push_back(G.rank[e]);
+                C.ch_pptr.push_back((int)q);
+            }
+            C.pr_tgt[q] = tgt[e];
+            C.pr_src[q] = G.in_off[e];
+        }
+        C.ch_pptr.push_back((int)ne);
+        for (int r : C.ch_rank) C.max_rank = std::max(C.max_rank, r);
     }
 }
 

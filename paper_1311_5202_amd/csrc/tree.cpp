@@ -14,6 +14,8 @@
 //   interaction field I = N^P \ N^C (an M2L); a near pair with a leaf is
 //   summed directly (P2P) between the two subtrees.  Every point pair is
 //   covered exactly once.
+// * A far pair whose point counts multiply to at most p2p_threshold is summed
+//   directly instead (its translation would cost more than the point pairs).
 // * Wedges: each cube face is cut into an m x m grid of cells; a direction
 //   belongs to the cell its central projection hits.  Cells of a parent level
 //   (2m) nest in cells of the child level (m).
@@ -238,7 +240,7 @@ void build_tree(Plan &P)
         L.level = l;
         L.w = P.root_w * std::ldexp(1.0, -l);
         L.hf = L.w >= P.lambda * (1.0 - 1e-9);
-        L.m = L.hf ? (int)std::lround(L.w / P.lambda) : 0;
+        L.m = L.hf ? P.opt.wedge_factor * (int)std::lround(L.w / P.lambda) : 0;
         L.nwedge = L.hf ? 6 * L.m * L.m : 1;
     }
     P.leaves.clear();
@@ -299,6 +301,9 @@ void build_lists(Plan &P)
                     if (cc < 0) continue;
                     if (cheb(P.cubes[cb], P.cubes[cc]) <= reach_c)
                         next.push_back({cb, cc});
+                    else if ((double)(P.cubes[cb].end - P.cubes[cb].start) * (double)(P.cubes[cc].end - P.cubes[cc].start) <=
+                             P.opt.p2p_threshold)
+                        p2p_raw.push_back({cb, cc});  // cheaper summed directly than translated
                     else
                         m2l_raw[l + 1].push_back({cb, cc});
                 }
