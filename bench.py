@@ -84,7 +84,7 @@ def main() -> int:
     pts, nrm, w = fdb.nystrom_nodes(el)
     N = len(w)
     t0 = time.perf_counter()
-    plan = fdb.build(pts, nrm, w, k, eps)
+    plan = fdb.build(pts, nrm, w, k, eps, elements=el, corrections=1, verbose=1)
     t_build = time.perf_counter() - t0
     st = plan.stats()
     print(f"[bench] workload={args.workload} N={N} k={k} p2p_pairs={st['p2p_pairs']} build {t_build:.1f} s m2l_tile={st.get('m2l_tile')} tiles(t,ch,p,seg)={st.get('m2l_tiles')} lds={st.get('m2l_lds_bytes')}/{st.get('max_lds_per_block')}", file=sys.stderr, flush=True)
@@ -113,7 +113,7 @@ def main() -> int:
     n_m2l_launch = max(1, sum(1 for L in st["levels"] if L["m2l_pairs"] > 0))
     roof = {
         "bound": "mfma",
-        "kernel": "k_gemv<M2L> (all levels of one mat-vec)",
+        "kernel": "M2L (all levels of one mat-vec)",
         "achieved": flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else 0.0,
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",

@@ -28,7 +28,7 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if src.endswith(".hip"):
-        cmd = [HIPCC, *COMMON, *DEVICE, "-c", src, "-o", obj]
+        cmd = [HIPCC, *COMMON, *DEVICE, "-fopenmp", "-c", src, "-o", obj]
     else:
         # host-only translation units (set-up, ABI): plain C++ with OpenMP
         cmd = [HIPCC, *COMMON, "-x", "c++", "-fopenmp", "-c", src, "-o", obj]

@@ -14,6 +14,7 @@
 //   un-permute, free term, near-field correction SpMV (caller order)
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <stdexcept>
@@ -562,15 +563,21 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_m2l_chunks(int n_chunks, in
     }
 }
 
-// Near-field correction, caller order: out_i += sum_c val_c in_{col_c}.
-__global__ void k_corr(const int64_t *__restrict__ rp, const int64_t *__restrict__ col,
+// Near-field correction, caller order: out_i += sum over the node's element
+// blocks of sum_g val_bg in_{6 e_b + g}.
+__global__ void k_corr(const int64_t *__restrict__ rp, const int32_t *__restrict__ blk,
                        const double2 *__restrict__ val, const double2 *__restrict__ in, double2 *__restrict__ out,
                        int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double2 acc = make_double2(0.0, 0.0);
-    for (int64_t c = rp[i]; c < rp[i + 1]; ++c) acc = cadd(acc, cmul(val[c], in[col[c]]));
+    for (int64_t b = rp[i]; b < rp[i + 1]; ++b) {
+        const double2 *u = in + 6 * (int64_t)blk[b];
+        const double2 *v = val + 6 * b;
+#pragma unroll
+        for (int g = 0; g < 6; ++g) acc = cadd(acc, cmul(v[g], u[g]));
+    }
     out[i] = cadd(out[i], acc);
 }
 
@@ -836,21 +843,15 @@ void device_upload(Plan &P)
     }
     D.dens = dalloc<double2>(D, P.N);
     D.res = dalloc<double2>(D, P.N);
-    if (P.has_corr) {
-        D.corr_nnz = (int64_t)P.corr_col.size();
-        D.corr_ptr = dupload(D, P.corr_ptr);
-        D.corr_col = dupload(D, P.corr_col);
-        std::vector<double2> cv(P.corr_val.size());
-        for (size_t i = 0; i < cv.size(); ++i) cv[i] = make_double2(P.corr_val[i].real(), P.corr_val[i].imag());
-        D.corr_val = dupload(D, cv);
-    }
-    if (P.has_corr_g) {
-        D.corrg_nnz = (int64_t)P.corrg_col.size();
-        D.corrg_ptr = dupload(D, P.corrg_ptr);
-        D.corrg_col = dupload(D, P.corrg_col);
-        std::vector<double2> cv(P.corrg_val.size());
-        for (size_t i = 0; i < cv.size(); ++i) cv[i] = make_double2(P.corrg_val[i].real(), P.corrg_val[i].imag());
-        D.corrg_val = dupload(D, cv);
+    if (P.n_elem > 0 && (P.opt.corrections & 3)) {
+        const auto t0 = std::chrono::steady_clock::now();
+        build_corrections_device(P, D);
+        P.t_setup_corr = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (P.opt.verbose) {
+            std::fprintf(stderr, "[fdbem] near-field corrections %.2f s (%lld element blocks)\n", P.t_setup_corr,
+                         (long long)P.corr_blocks);
+            std::fflush(stderr);
+        }
     }
     D.ev.assign((size_t)Device::kRing * 10, nullptr);
     for (auto &e : D.ev) HIP_CHECK(hipEventCreate(&e));
@@ -971,10 +972,10 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
     if (tm) HIP_CHECK(hipEventRecord(ev[7], st));
     hipLaunchKernelGGL(k_permute_out, dim3(nblk(N, 256)), dim3(256), 0, st, D.res, D.perm, in, op == 3 ? 0.5 : 0.0, out, N);
     if (tm) HIP_CHECK(hipEventRecord(ev[8], st));
-    if (op == 3 && D.corr_nnz)
-        hipLaunchKernelGGL(k_corr, dim3(nblk(N, 256)), dim3(256), 0, st, D.corr_ptr, D.corr_col, D.corr_val, in, out, N);
-    if (op == 4 && D.corrg_nnz)
-        hipLaunchKernelGGL(k_corr, dim3(nblk(N, 256)), dim3(256), 0, st, D.corrg_ptr, D.corrg_col, D.corrg_val, in, out,
+    if (op == 3 && D.corr.val)
+        hipLaunchKernelGGL(k_corr, dim3(nblk(N, 256)), dim3(256), 0, st, D.corr.rp, D.corr.blk, D.corr.val, in, out, N);
+    if (op == 4 && D.corrg.val)
+        hipLaunchKernelGGL(k_corr, dim3(nblk(N, 256)), dim3(256), 0, st, D.corrg.rp, D.corrg.blk, D.corrg.val, in, out,
                            N);
     if (tm) {
         HIP_CHECK(hipEventRecord(ev[9], st));

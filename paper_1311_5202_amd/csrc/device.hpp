@@ -33,6 +33,13 @@ struct DChunks {
     int *ch_rank = nullptr, *ch_pptr = nullptr;
 };
 
+struct DCorr {
+    int64_t n_blocks = 0;
+    int64_t *rp = nullptr;    // per node: block range
+    int32_t *blk = nullptr;   // per block: element (columns 6e .. 6e+5)
+    double2 *val = nullptr;   // per block: 6 complex weights
+};
+
 struct DLeaf {
     int n = 0;
     int64_t *start = nullptr, *end = nullptr, *slot = nullptr;
@@ -70,13 +77,8 @@ struct Device {
     double2 *res = nullptr;      // sorted result (N)
     double2 *od = nullptr, *id = nullptr;
     int64_t n_od = 0, n_id = 0;
-    // near-field correction (caller order, CSR)
-    int64_t corr_nnz = 0;
-    int64_t *corr_ptr = nullptr, *corr_col = nullptr;
-    double2 *corr_val = nullptr;
-    int64_t corrg_nnz = 0;
-    int64_t *corrg_ptr = nullptr, *corrg_col = nullptr;
-    double2 *corrg_val = nullptr;
+    // near-field corrections (caller order, block CSR: 6 columns per element)
+    DCorr corr, corrg;
     // GMRES work space (allocated on first solve)
     int gm_m = 0;
     double2 *gm_V = nullptr, *gm_w = nullptr, *gm_x = nullptr, *gm_r = nullptr, *gm_h = nullptr;
@@ -94,6 +96,7 @@ struct Device {
 void device_upload(Plan &P);
 void device_free(Plan &P);
 void device_phase_average(Plan &P);
+void build_corrections_device(Plan &P, Device &D);
 void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st);
 void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t st);
 int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int restart, int precond, double2 *x,

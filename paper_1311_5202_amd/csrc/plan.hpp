@@ -164,14 +164,9 @@ struct Plan {
     std::vector<LeafTask> s2m_tasks, l2t_tasks;
     int64_t out_total = 0, in_total = 0;         // density array sizes
     int max_s = 0, max_Y = 0, max_Y_leaf = 0;
-    // near-field correction (sparse, caller order): row ptr, col, complex weight
-    std::vector<int64_t> corr_ptr;
-    std::vector<int64_t> corr_col;
-    std::vector<cplx> corr_val;
-    bool has_corr = false;
-    std::vector<int64_t> corrg_ptr, corrg_col;   // same for the G operator
-    std::vector<cplx> corrg_val;
-    bool has_corr_g = false;
+    // near-field correction tables (built on the device, caller order, blocks of 6)
+    bool has_corr = false, has_corr_g = false;
+    int64_t corr_blocks = 0;
     // statistics
     std::string stats_json;
     double t_setup_tree = 0, t_setup_tmpl = 0, t_setup_ops = 0, t_setup_corr = 0;
@@ -184,7 +179,6 @@ void build_tree(Plan &P);
 void build_lists(Plan &P);
 void build_templates(Plan &P);
 void build_operators(Plan &P);
-void build_corrections(Plan &P);
 void build_m2l_tiles(Plan &P, int tile, int chunk);
 void build_m2l_chunks(Plan &P, int chunk);
 void correction_table_host(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,

@@ -1,6 +1,7 @@
 // Host-side plan construction: copies the caller's geometry, sorts it into
 // octree order and runs the FP64 set-up stages.
 #include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <sstream>
 #include <stdexcept>
@@ -53,22 +54,27 @@ Plan *plan_create_host(int64_t n, const double *pts, const double *nrm, const do
             P->n_elem = n_elem;
             P->elem.assign(elem, elem + 18 * n_elem);
         }
+        auto log = [&](const char *what, double t) {
+            if (P->opt.verbose) {
+                std::fprintf(stderr, "[fdbem] %s %.2f s\n", what, t);
+                std::fflush(stderr);
+            }
+        };
         double t0 = now_s();
         build_tree(*P);
+        log("octree", now_s() - t0);
         build_lists(*P);
         double t1 = now_s();
         P->t_setup_tree = t1 - t0;
+        log("lists", P->t_setup_tree);
         if (P->opt.far_field) {
             build_templates(*P);
             double t2 = now_s();
             P->t_setup_tmpl = t2 - t1;
+            log("templates", P->t_setup_tmpl);
             build_operators(*P);
             P->t_setup_ops = now_s() - t2;
-        }
-        if (n_elem > 0 && P->opt.corrections) {
-            double t3 = now_s();
-            build_corrections(*P);
-            P->t_setup_corr = now_s() - t3;
+            log("translation operators", P->t_setup_ops);
         }
     } catch (...) {
         delete P;
@@ -85,7 +91,7 @@ std::string plan_stats(const Plan &P)
       << ", \"root_w\": " << P.root_w << ", \"n_levels\": " << P.levels.size() << ", \"n_leaves\": " << P.leaves.size()
       << ", \"p2p_pairs\": " << P.p2p_pairs << ", \"matpool_bytes\": " << P.matpool.size() * 16
       << ", \"density_slots_out\": " << P.out_total << ", \"density_slots_in\": " << P.in_total
-      << ", \"corr_nnz\": " << P.corr_col.size() << ", \"setup_s\": {\"tree\": " << P.t_setup_tree
+      << ", \"corr_nnz\": " << 6 * P.corr_blocks << ", \"setup_s\": {\"tree\": " << P.t_setup_tree
       << ", \"templates\": " << P.t_setup_tmpl << ", \"operators\": " << P.t_setup_ops
       << ", \"corrections\": " << P.t_setup_corr << "}, \"levels\": [";
     for (size_t l = 0; l < P.levels.size(); ++l) {
