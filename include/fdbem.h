@@ -83,7 +83,7 @@ typedef struct {
     int wedge_factor;   /* directional wedges: cells per cube-face edge = wedge_factor * w / lambda; 0 -> 2 */
     int m2l_tile;       /* M2L target tile size; 0 -> largest that fits LDS, < 0 -> per-target kernel */
     double p2p_threshold; /* a far pair whose point counts multiply to at most this is summed
-                             directly instead of translated; 0 -> 1024, < 0 -> never */
+                             directly instead of translated; 0 -> 400, < 0 -> never */
 } fda_opts;
 
 typedef struct fda_plan fda_plan;

@@ -494,7 +494,8 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(64 * M2LC_WAVES) void k_m2l_chunks(int n_chunks, int s, int rmax,
+template <int TAG, bool TRANS>
+__global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks(int n_chunks, int s, int cols, int rmax,
                                                                 const int64_t *__restrict__ ch_mat,
                                                                 const int *__restrict__ ch_rank,
                                                                 const int *__restrict__ ch_pptr,
@@ -507,31 +508,27 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_m2l_chunks(int n_chunks, in
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * M2LC_WAVES + wv;
     if (c >= n_chunks) return;
-    double2 *X = sh + (size_t)wv * (M2LC_CH * s + M2LC_CH * rmax);
-    double2 *T = X + M2LC_CH * s;
+    // s: output rows, cols: input length (both equal for M2L)
+    double2 *X = sh + (size_t)wv * (M2LC_CH * cols + M2LC_CH * rmax);
+    double2 *T = X + M2LC_CH * cols;
     const int p0 = ch_pptr[c], n = ch_pptr[c + 1] - p0;
-    for (int i = lane; i < n * s; i += 64) {
-        const int p = i / s, j = i - p * s;
-        X[p * s + j] = od[pr_src[p0 + p] + j];
+    for (int i = lane; i < n * cols; i += 64) {
+        const int p = i / cols, j = i - p * cols;
+        X[p * cols + j] = od[pr_src[p0 + p] + j];
     }
     wave_sync();
     const double2 *M = mat + ch_mat[c];
     const int r = ch_rank[c];
     double2 acc[M2LC_CH];
     if (r >= 0) {
+        // t = V x for every (rank index, pair) item of the chunk
         const double2 *V = M + (size_t)s * r;
-        for (int qq = lane; qq < r; qq += 64) {
-#pragma unroll
-            for (int p = 0; p < M2LC_CH; ++p) acc[p] = make_double2(0.0, 0.0);
-            for (int j = 0; j < s; ++j) {
-                const double2 m = V[qq + (size_t)j * r];
-#pragma unroll
-                for (int p = 0; p < M2LC_CH; ++p)
-                    if (p < n) acc[p] = cadd(acc[p], cmul(m, X[p * s + j]));
-            }
-#pragma unroll
-            for (int p = 0; p < M2LC_CH; ++p)
-                if (p < n) T[p * rmax + qq] = acc[p];
+        for (int it = lane; it < r * n; it += 64) {
+            const int p = it / r, qq = it - p * r;
+            const double2 *xp = X + p * s;
+            double2 a = make_double2(0.0, 0.0);
+            for (int j = 0; j < s; ++j) a = cadd(a, cmul(V[qq + (size_t)j * r], xp[j]));
+            T[p * rmax + qq] = a;
         }
         wave_sync();
     }
@@ -539,11 +536,12 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_m2l_chunks(int n_chunks, in
 #pragma unroll
         for (int p = 0; p < M2LC_CH; ++p) acc[p] = make_double2(0.0, 0.0);
         if (r < 0) {
-            for (int j = 0; j < s; ++j) {
-                const double2 m = M[row + (size_t)j * s];
+            for (int j = 0; j < cols; ++j) {
+                // dense operator s x cols, or its transpose stored cols x s
+                const double2 m = TRANS ? M[j + (size_t)row * cols] : M[row + (size_t)j * s];
 #pragma unroll
                 for (int p = 0; p < M2LC_CH; ++p)
-                    if (p < n) acc[p] = cadd(acc[p], cmul(m, X[p * s + j]));
+                    if (p < n) acc[p] = cadd(acc[p], cmul(m, X[p * cols + j]));
             }
         } else {
             for (int qq = 0; qq < r; ++qq) {
@@ -661,9 +659,10 @@ static DChunks upload_chunks(Device &D, const M2LChunks &C)
     DChunks d;
     d.n = (int)C.ch_mat.size();
     d.s = C.s;
+    d.cols = C.cols;
     d.rmax = std::max(1, C.max_rank);
     if (d.n == 0) return d;
-    d.shm = sizeof(double2) * (size_t)M2LC_WAVES * (M2LC_CH * d.s + M2LC_CH * d.rmax);
+    d.shm = sizeof(double2) * (size_t)M2LC_WAVES * (M2LC_CH * d.cols + M2LC_CH * d.rmax);
     d.ch_mat = dupload(D, C.ch_mat);
     d.ch_rank = dupload(D, C.ch_rank);
     d.ch_pptr = dupload(D, C.ch_pptr);
@@ -771,10 +770,19 @@ void device_upload(Plan &P)
                                         (int64_t)P.m2l_chunks[l].pr_tgt.size(), 0});
                 if (D.m2lc[l].shm > (size_t)maxsh) D.m2l_mode = 1;
                 if (D.m2lc[l].shm > 65536)
-                    HIP_CHECK(hipFuncSetAttribute((const void *)k_m2l_chunks,
+                    HIP_CHECK(hipFuncSetAttribute((const void *)k_chunks<TAG_M2L, false>,
                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)D.m2lc[l].shm));
             }
             P.m2l_chunks.clear();
+            // up and down passes by operator chunks as well
+            D.m2mc.resize(nlev);
+            D.l2lc.resize(nlev);
+            for (int l = 0; l < nlev; ++l) {
+                D.m2mc[l] = upload_chunks(D, build_chunks(P.m2m_lists[l], M2LC_CH));
+                D.l2lc[l] = upload_chunks(D, build_chunks(P.l2l_lists[l], M2LC_CH));
+                for (const DChunks *c : {&D.m2mc[l], &D.l2lc[l]})
+                    if (c->shm > (size_t)maxsh) throw std::runtime_error("translation operator too large for LDS");
+            }
         }
         if (D.m2l_mode == 2) {
             // deterministic tiles: the largest tile whose LDS footprint fits one workgroup
@@ -937,15 +945,24 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
                                D.s2m.slot, D.s2m.tmpl, D.s2m.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, D.t_W,
                                D.x, D.y, D.z, D.nx, D.ny, D.nz, D.dens, D.od, P.k, c);
         if (tm) HIP_CHECK(hipEventRecord(ev[3], st));
-        for (int l = D.n_lev - 2; l >= 0; --l) run_gemv<TAG_M2M>(D.m2m[l], D.mat, D.od, D.od, st);
+        for (int l = D.n_lev - 2; l >= 0; --l) {
+            if (D.m2l_mode == 0) {
+                const DChunks &C = D.m2mc[l];
+                if (C.n)
+                    hipLaunchKernelGGL((k_chunks<TAG_M2M, false>), dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES),
+                                       dim3(64 * M2LC_WAVES), C.shm, st, C.n, C.s, C.cols, C.rmax, C.ch_mat, C.ch_rank,
+                                       C.ch_pptr, C.pr_tgt, C.pr_src, D.mat, D.od, D.od);
+            } else
+                run_gemv<TAG_M2M>(D.m2m[l], D.mat, D.od, D.od, st);
+        }
         if (tm) HIP_CHECK(hipEventRecord(ev[4], st));
         for (int l = 0; l < D.n_lev; ++l) {
             if (D.m2l_mode == 0) {
                 const DChunks &C = D.m2lc[l];
                 if (C.n)
-                    hipLaunchKernelGGL(k_m2l_chunks, dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES), dim3(64 * M2LC_WAVES),
-                                       C.shm, st, C.n, C.s, C.rmax, C.ch_mat, C.ch_rank, C.ch_pptr, C.pr_tgt,
-                                       C.pr_src, D.mat, D.od, D.id);
+                    hipLaunchKernelGGL((k_chunks<TAG_M2L, false>), dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES),
+                                       dim3(64 * M2LC_WAVES), C.shm, st, C.n, C.s, C.s, C.rmax, C.ch_mat, C.ch_rank,
+                                       C.ch_pptr, C.pr_tgt, C.pr_src, D.mat, D.od, D.id);
             } else if (D.m2l_mode == 2) {
                 const DTiles &T = D.m2lt[l];
                 if (T.n_tiles) {
@@ -960,7 +977,16 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
                 run_gemv<TAG_M2L>(D.m2l[l], D.mat, D.od, D.id, st);
         }
         if (tm) HIP_CHECK(hipEventRecord(ev[5], st));
-        for (int l = 1; l < D.n_lev; ++l) run_gemv<TAG_L2L>(D.l2l[l], D.mat, D.id, D.id, st);
+        for (int l = 1; l < D.n_lev; ++l) {
+            if (D.m2l_mode == 0) {
+                const DChunks &C = D.l2lc[l];
+                if (C.n)
+                    hipLaunchKernelGGL((k_chunks<TAG_L2L, true>), dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES),
+                                       dim3(64 * M2LC_WAVES), C.shm, st, C.n, C.s, C.cols, C.rmax, C.ch_mat, C.ch_rank,
+                                       C.ch_pptr, C.pr_tgt, C.pr_src, D.mat, D.id, D.id);
+            } else
+                run_gemv<TAG_L2L>(D.l2l[l], D.mat, D.id, D.id, st);
+        }
         if (tm) HIP_CHECK(hipEventRecord(ev[6], st));
         if (D.l2t.n)
             hipLaunchKernelGGL(k_l2t, dim3(D.l2t.n), dim3(LEAF_BLOCK), shm_leaf, st, D.l2t.start, D.l2t.end,

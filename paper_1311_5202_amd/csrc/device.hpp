@@ -27,7 +27,7 @@ struct DTiles {
 };
 
 struct DChunks {
-    int n = 0, s = 0, rmax = 1;
+    int n = 0, s = 0, cols = 0, rmax = 1;
     size_t shm = 0;
     int64_t *ch_mat = nullptr, *pr_tgt = nullptr, *pr_src = nullptr;
     int *ch_rank = nullptr, *ch_pptr = nullptr;
@@ -68,6 +68,7 @@ struct Device {
     std::vector<DGemv> m2m, m2l, l2l;  // per level
     std::vector<DTiles> m2lt;          // per level, tiled M2L
     std::vector<DChunks> m2lc;         // per level, operator-chunk M2L
+    std::vector<DChunks> m2mc, l2lc;   // per level, operator-chunk M2M and L2L
     int m2l_mode = 0;                  // 0 operator chunks, 1 per-target GEMV, 2 target tiles
     double2 *m2l_part = nullptr;       // partial sums of split tiles
     std::vector<std::array<int64_t, 4>> tile_stats;  // per level: tiles, chunks, pairs, segments

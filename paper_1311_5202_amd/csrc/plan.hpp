@@ -22,7 +22,7 @@ struct Options {
     int leaf_rule = 0;       // 0: leaves are low-frequency cubes (w < lambda)
     int wedge_factor = 2;    // wedge cells per face edge = wedge_factor * w / lambda
     int m2l_tile = 0;        // M2L target tile (0 auto, <0 per-target GEMV kernel)
-    double p2p_threshold = 1024;  // far pairs with n_B * n_C <= this are summed directly
+    double p2p_threshold = 400;   // far pairs with n_B * n_C <= this are summed directly
     double c_d = 1.0 / M_PI; // high-frequency near-field constant
     int far_field = 1;       // 0: every pair by direct summation (debug / tiny problems)
     int lf_grid = 0;         // points per edge of the low-frequency surface grids (0 -> auto)
@@ -117,7 +117,7 @@ struct M2LTiles {
 // of at most `chunk` pairs; one wavefront applies the operator to a chunk and
 // adds the results to the targets with FP64 atomics.
 struct M2LChunks {
-    int chunk = 0, s = 0, max_rank = 0;
+    int chunk = 0, s = 0, cols = 0, max_rank = 0, trans = 0;
     std::vector<int64_t> ch_mat;
     std::vector<int> ch_rank, ch_pptr;
     std::vector<int64_t> pr_tgt, pr_src;
@@ -181,6 +181,7 @@ void build_templates(Plan &P);
 void build_operators(Plan &P);
 void build_m2l_tiles(Plan &P, int tile, int chunk);
 void build_m2l_chunks(Plan &P, int chunk);
+M2LChunks build_chunks(const GemvList &G, int chunk);
 void correction_table_host(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,
                            double k, int op, std::vector<int64_t> &rp, std::vector<int64_t> &col,
                            std::vector<cplx> &val);

@@ -528,42 +528,47 @@ void build_m2l_tiles(Plan &P, int tile, int chunk)
 
 namespace fdbem {
 
+M2LChunks build_chunks(const GemvList &G, int chunk)
+{
+    M2LChunks C;
+    C.chunk = chunk;
+    C.s = G.rows;
+    C.cols = G.cols;
+    C.trans = G.trans;
+    const int n_out = (int)G.out_off.size();
+    if (n_out == 0) return C;
+    const int64_t ne = (int64_t)G.in_off.size();
+    std::vector<int64_t> tgt(ne);
+    for (int o = 0; o < n_out; ++o)
+        for (int e = G.ptr[o]; e < G.ptr[o + 1]; ++e) tgt[e] = G.out_off[o];
+    std::vector<int64_t> idx(ne);
+    for (int64_t e = 0; e < ne; ++e) idx[e] = e;
+    // by operator, then by target (nearby targets share cache lines)
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        return G.mat_off[a] != G.mat_off[b] ? G.mat_off[a] < G.mat_off[b] : tgt[a] < tgt[b];
+    });
+    C.pr_tgt.resize(ne);
+    C.pr_src.resize(ne);
+    for (int64_t q = 0; q < ne; ++q) {
+        const int64_t e = idx[q];
+        if (q == 0 || G.mat_off[e] != G.mat_off[idx[q - 1]] || (q - C.ch_pptr.back()) >= chunk) {
+            C.ch_mat.push_back(G.mat_off[e]);
+            C.ch_rank.push_back(G.rank[e]);
+            C.ch_pptr.push_back((int)q);
+        }
+        C.pr_tgt[q] = tgt[e];
+        C.pr_src[q] = G.in_off[e];
+    }
+    C.ch_pptr.push_back((int)ne);
+    for (int r : C.ch_rank) C.max_rank = std::max(C.max_rank, r);
+    return C;
+}
+
 void build_m2l_chunks(Plan &P, int chunk)
 {
     const int nlev = (int)P.levels.size();
     P.m2l_chunks.assign(nlev, M2LChunks());
-    for (int l = 0; l < nlev; ++l) {
-        const GemvList &G = P.m2l_lists[l];
-        M2LChunks &C = P.m2l_chunks[l];
-        C.chunk = chunk;
-        C.s = G.rows;
-        const int n_out = (int)G.out_off.size();
-        if (n_out == 0) continue;
-        const int64_t ne = (int64_t)G.in_off.size();
-        std::vector<int64_t> tgt(ne);
-        for (int o = 0; o < n_out; ++o)
-            for (int e = G.ptr[o]; e < G.ptr[o + 1]; ++e) tgt[e] = G.out_off[o];
-        std::vector<int64_t> idx(ne);
-        for (int64_t e = 0; e < ne; ++e) idx[e] = e;
-        // by operator, then by target (nearby targets share cache lines)
-        std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-            return G.mat_off[a] != G.mat_off[b] ? G.mat_off[a] < G.mat_off[b] : tgt[a] < tgt[b];
-        });
-        C.pr_tgt.resize(ne);
-        C.pr_src.resize(ne);
-        for (int64_t q = 0; q < ne; ++q) {
-            const int64_t e = idx[q];
-            if (q == 0 || G.mat_off[e] != G.mat_off[idx[q - 1]] || (q - C.ch_pptr.back()) >= chunk) {
-                C.ch_mat.push_back(G.mat_off[e]);
-                C.ch_rank.push_back(G.rank[e]);
-                C.ch_pptr.push_back((int)q);
-            }
-            C.pr_tgt[q] = tgt[e];
-            C.pr_src[q] = G.in_off[e];
-        }
-        C.ch_pptr.push_back((int)ne);
-        for (int r : C.ch_rank) C.max_rank = std::max(C.max_rank, r);
-    }
+    for (int l = 0; l < nlev; ++l) P.m2l_chunks[l] = build_chunks(P.m2l_lists[l], chunk);
 }
 
 }  // namespace fdbem
