@@ -53,7 +53,13 @@ enum {
     FDA_OP_BM_G = 4    /* sum_j Gbar_ij q_j: corrected G sum (needs elements)                */
 };
 
-enum { FDA_PREC_FP64 = 0, FDA_PREC_FP32 = 1 };
+/* OR'ed into an operator code: evaluate the near-field point sum and the far
+ * field (S2M .. L2T) in FP32 (differences of positions and the correction
+ * SpMV stay FP64).  Needs a plan built with FDA_PREC_FP32 or FDA_PREC_BOTH;
+ * on an FP32-only plan it is implied. */
+#define FDA_OP_FP32 0x100
+
+enum { FDA_PREC_FP64 = 0, FDA_PREC_FP32 = 1, FDA_PREC_BOTH = 2 };
 
 /* Geometry: Nystrom nodes with normals and weights; optionally the curved
  * quadratic elements they come from (needed for the local corrections).
@@ -77,7 +83,7 @@ typedef struct {
     double c_d;         /* high-frequency near-field constant (section 3.1.1); 0 -> 1/pi  */
     int far_field;      /* 1: fast directional far field; 0: all pairs summed directly    */
     int lf_grid;        /* points per edge of low-frequency surface grids; 0 -> from eps  */
-    int precision;      /* FDA_PREC_FP64 or FDA_PREC_FP32 (far field and P2P in FP32)     */
+    int precision;      /* FDA_PREC_FP64, FDA_PREC_FP32 or FDA_PREC_BOTH (see FDA_OP_FP32) */
     int corrections;    /* bit 0: corrected H table, bit 1: corrected G table (needs elements) */
     int verbose;
     int wedge_factor;   /* directional wedges: cells per cube-face edge = wedge_factor * w / lambda; 0 -> 2 */

@@ -18,6 +18,8 @@ FDA_EBREAKDOWN = -6
 FDA_ENOTSUP = -7
 
 OPS = {"RAW_H": 0, "RAW_G": 1, "RAW_T1": 2, "BM_H": 3, "BM_G": 4}
+FDA_OP_FP32 = 0x100
+PREC = {"fp64": 0, "fp32": 1, "both": 2}
 
 EXPORTS = ("fda_default_opts", "bem_nystrom_nodes", "bem_near_correction", "fda_build", "fda_matvec", "bm_solve", "fda_rhs_plane_wave",
            "fda_stats", "fda_set_timing", "fda_phase_times", "fda_destroy", "fda_last_error")

@@ -124,7 +124,7 @@ int fda_build(const fda_geometry *g, double k, double eps, const fda_opts *o, fd
             opt.m2l_tile = o->m2l_tile;
             if (o->p2p_threshold != 0) opt.p2p_threshold = o->p2p_threshold;
         }
-        if (opt.precision != FDA_PREC_FP64) throw std::invalid_argument("precision not available in this build");
+        if (opt.precision < FDA_PREC_FP64 || opt.precision > FDA_PREC_BOTH) throw std::invalid_argument("unknown precision");
         if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");
         Plan *P = plan_create_host(g->n_nodes, g->pts, g->nrm, g->w, g->n_elem, g->elem, k, eps, opt);
         try {
@@ -144,12 +144,15 @@ int fda_matvec(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *
 {
     return guarded([&] {
         if (!plan || !in_dev || !out_dev) throw std::invalid_argument("null argument");
-        if (op < FDA_OP_RAW_H || op > FDA_OP_BM_G) throw std::invalid_argument("unknown operator");
+        const int base = op & 0xff;
+        if (base < FDA_OP_RAW_H || base > FDA_OP_BM_G || (op & ~0x1ff)) throw std::invalid_argument("unknown operator");
         if (in_dev == out_dev) throw std::invalid_argument("input and output must not alias");
         Plan &P = *plan->P;
-        if (op == FDA_OP_BM_H && !P.has_corr)
+        if ((op & FDA_OP_FP32) && P.opt.precision == FDA_PREC_FP64)
+            throw std::invalid_argument("FP32 operator requested on an FP64-only plan");
+        if (base == FDA_OP_BM_H && !P.has_corr)
             throw std::invalid_argument("the corrected H operator needs a plan built with elements");
-        if (op == FDA_OP_BM_G && !P.has_corr_g)
+        if (base == FDA_OP_BM_G && !P.has_corr_g)
             throw std::invalid_argument("the corrected G operator needs a plan built with elements and corrections & 2");
         device_matvec(P, op, (const double2 *)in_dev, (double2 *)out_dev, (hipStream_t)stream);
         return FDA_OK;
@@ -162,9 +165,12 @@ int bm_solve(fda_plan *plan, int op, const void *rhs_dev, double tol, int maxit,
     return guarded([&] {
         if (!plan || !rhs_dev || !x_dev) throw std::invalid_argument("null argument");
         if (!(tol > 0) || maxit < 1 || restart < 1) throw std::invalid_argument("bad solver parameters");
-        if (op < FDA_OP_RAW_H || op > FDA_OP_BM_G) throw std::invalid_argument("unknown operator");
+        const int base = op & 0xff;
+        if (base < FDA_OP_RAW_H || base > FDA_OP_BM_G || (op & ~0x1ff)) throw std::invalid_argument("unknown operator");
         Plan &P = *plan->P;
-        if ((op == FDA_OP_BM_H && !P.has_corr) || (op == FDA_OP_BM_G && !P.has_corr_g))
+        if ((op & FDA_OP_FP32) && P.opt.precision == FDA_PREC_FP64)
+            throw std::invalid_argument("FP32 operator requested on an FP64-only plan");
+        if ((base == FDA_OP_BM_H && !P.has_corr) || (base == FDA_OP_BM_G && !P.has_corr_g))
             throw std::invalid_argument("corrected operators need a plan built with elements");
         const int rc = device_gmres(P, op, (const double2 *)rhs_dev, tol, maxit, restart, precond, (double2 *)x_dev,
                                     iters_out, relres_out, resid_hist, (hipStream_t)stream);

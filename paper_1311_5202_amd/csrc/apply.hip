@@ -36,6 +36,9 @@ struct OpC {
     double2 cd00, cd10, cd01, cd11;  // products c_a d_b of K = (c0 + c1 d/dn_y)(d0 + d1 d/dn_x) G
     double2 c0, c1, d0, d1;
 };
+struct OpCf {
+    float2 c0, c1, d0, d1;
+};
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
@@ -43,6 +46,30 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// complex type and elementary functions for the working precision R
+template <typename R> struct Cx;
+template <> struct Cx<double> {
+    using T = double2;
+    __device__ static T mk(double a, double b) { return make_double2(a, b); }
+    __device__ static void sc(double x, double *s, double *c) { sincos(x, s, c); }
+    __device__ static double rs(double x) { return rsqrt(x); }
+};
+template <> struct Cx<float> {
+    using T = float2;
+    __device__ static T mk(float a, float b) { return make_float2(a, b); }
+    __device__ static void sc(float x, float *s, float *c) { sincosf(x, s, c); }
+    __device__ static float rs(float x) { return rsqrtf(x); }
+};
+__device__ __forceinline__ double2 to64(double2 a) { return a; }
+__device__ __forceinline__ double2 to64(float2 a) { return make_double2(a.x, a.y); }
+template <typename C> __device__ __forceinline__ C from64(double2 a);
+template <> __device__ __forceinline__ double2 from64<double2>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 from64<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
 
 constexpr double kInv4Pi = 0.07957747154594767;  // 1/(4 pi)
 
@@ -71,42 +98,45 @@ __device__ __forceinline__ double2 kernel_full(double dx, double dy, double dz, 
 }
 
 // Source-side kernel (c0 + c1 d/dn_y) G at a point x without normal.
-__device__ __forceinline__ double2 kernel_src(double dx, double dy, double dz, double nyx, double nyy, double nyz,
-                                              double k, const OpC &c)
+template <typename R, typename O>
+__device__ __forceinline__ typename Cx<R>::T kernel_src(R dx, R dy, R dz, R nyx, R nyy, R nyz, R k, const O &c)
 {
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double r = sqrt(r2);
-    const double ir = 1.0 / r;
-    double sn, cs;
-    sincos(k * r, &sn, &cs);
-    const double g = ir * kInv4Pi;
-    const double2 G = make_double2(cs * g, sn * g);
-    const double dny = (dx * nyx + dy * nyy + dz * nyz) * ir;
-    const double2 a = make_double2(ir, -k);
+    using C = typename Cx<R>::T;
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const R ir = Cx<R>::rs(r2);
+    const R r = r2 * ir;
+    R sn, cs;
+    Cx<R>::sc(k * r, &sn, &cs);
+    const R g = ir * (R)kInv4Pi;
+    const C G = Cx<R>::mk(cs * g, sn * g);
+    const R dny = (dx * nyx + dy * nyy + dz * nyz) * ir;
+    const C a = Cx<R>::mk(ir, -k);
     return cmul(G, cadd(c.c0, cmul(c.c1, cscale(a, dny))));
 }
 
 // Target-side kernel (d0 + d1 d/dn_x) G from a point y without normal.
-__device__ __forceinline__ double2 kernel_tgt(double dx, double dy, double dz, double nxx, double nxy, double nxz,
-                                              double k, const OpC &c)
+template <typename R, typename O>
+__device__ __forceinline__ typename Cx<R>::T kernel_tgt(R dx, R dy, R dz, R nxx, R nxy, R nxz, R k, const O &c)
 {
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double r = sqrt(r2);
-    const double ir = 1.0 / r;
-    double sn, cs;
-    sincos(k * r, &sn, &cs);
-    const double g = ir * kInv4Pi;
-    const double2 G = make_double2(cs * g, sn * g);
-    const double dnx = (dx * nxx + dy * nxy + dz * nxz) * ir;
-    const double2 a = make_double2(ir, -k);
+    using C = typename Cx<R>::T;
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const R ir = Cx<R>::rs(r2);
+    const R r = r2 * ir;
+    R sn, cs;
+    Cx<R>::sc(k * r, &sn, &cs);
+    const R g = ir * (R)kInv4Pi;
+    const C G = Cx<R>::mk(cs * g, sn * g);
+    const R dnx = (dx * nxx + dy * nxy + dz * nxz) * ir;
+    const C a = Cx<R>::mk(ir, -k);
     return cmul(G, cadd(c.d0, cmul(c.d1, cscale(a, -dnx))));
 }
 
 // ---------------------------------------------------------------- kernels
-__global__ void k_fill_zero(double2 *p, int64_t n)
+template <typename C>
+__global__ void k_fill_zero(C *p, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = make_double2(0.0, 0.0);
+    if (i < n) p[i].x = 0, p[i].y = 0;
 }
 
 __global__ void k_permute_in(const double2 *__restrict__ in, const int64_t *__restrict__ perm,
@@ -138,50 +168,52 @@ struct PN {
 
 enum { OPK_H = 0, OPK_G = 1, OPK_T1 = 2 };
 
-template <int OPK>
-__device__ __forceinline__ double2 kernel_op(double dx, double dy, double dz, double nxx, double nxy, double nxz,
-                                             double nyx, double nyy, double nyz, double k, double ik)
+template <int OPK, typename R>
+__device__ __forceinline__ typename Cx<R>::T kernel_op(R dx, R dy, R dz, R nxx, R nxy, R nxz, R nyx, R nyy, R nyz, R k,
+                                                       R ik)
 {
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double ir = rsqrt(r2);
-    const double r = r2 * ir;
-    double sn, cs;
-    sincos(k * r, &sn, &cs);
-    const double g = ir * kInv4Pi;
-    const double2 G = make_double2(cs * g, sn * g);
-    const double2 a = make_double2(ir, -k);  // 1/r - ik
-    double2 t;
+    using C = typename Cx<R>::T;
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const R ir = Cx<R>::rs(r2);
+    const R r = r2 * ir;
+    R sn, cs;
+    Cx<R>::sc(k * r, &sn, &cs);
+    const R g = ir * (R)kInv4Pi;
+    const C G = Cx<R>::mk(cs * g, sn * g);
+    const C a = Cx<R>::mk(ir, -k);  // 1/r - ik
+    C t;
     if (OPK == OPK_H) {
         // dG/dn_y + alpha d2G/dn_x dn_y, alpha = i/k
-        const double dnx = (dx * nxx + dy * nxy + dz * nxz) * ir;
-        const double dny = (dx * nyx + dy * nyy + dz * nyz) * ir;
-        const double nn = nxx * nyx + nxy * nyy + nxz * nyz;
-        const double2 q = make_double2(k * k - 3.0 * ir * ir, 3.0 * k * ir);
-        const double p = dnx * dny, f = nn * ir;
-        const double2 B = make_double2(q.x * p + a.x * f, q.y * p + a.y * f);
-        t = make_double2(a.x * dny - B.y * ik, a.y * dny + B.x * ik);
+        const R dnx = (dx * nxx + dy * nxy + dz * nxz) * ir;
+        const R dny = (dx * nyx + dy * nyy + dz * nyz) * ir;
+        const R nn = nxx * nyx + nxy * nyy + nxz * nyz;
+        const C q = Cx<R>::mk(k * k - (R)3 * ir * ir, (R)3 * k * ir);
+        const R p = dnx * dny, f = nn * ir;
+        const C B = Cx<R>::mk(q.x * p + a.x * f, q.y * p + a.y * f);
+        t = Cx<R>::mk(a.x * dny - B.y * ik, a.y * dny + B.x * ik);
     } else if (OPK == OPK_G) {
         // G + alpha dG/dn_x = G [1 - alpha a (d.n_x)/r]
-        const double dnx = (dx * nxx + dy * nxy + dz * nxz) * ir;
-        t = make_double2(1.0 + a.y * dnx * ik, -a.x * dnx * ik);
+        const R dnx = (dx * nxx + dy * nxy + dz * nxz) * ir;
+        t = Cx<R>::mk((R)1 + a.y * dnx * ik, -a.x * dnx * ik);
     } else {
         // G + alpha dG/dn_y = G [1 + alpha a (d.n_y)/r]
-        const double dny = (dx * nyx + dy * nyy + dz * nyz) * ir;
-        t = make_double2(1.0 - a.y * dny * ik, a.x * dny * ik);
+        const R dny = (dx * nyx + dy * nyy + dz * nyz) * ir;
+        t = Cx<R>::mk((R)1 - a.y * dny * ik, a.x * dny * ik);
     }
     return cmul(G, t);
 }
 
-template <int OPK>
+template <int OPK, typename R>
 __global__ __launch_bounds__(256) void k_p2p(int n_leaf, const int64_t *__restrict__ ts, const int64_t *__restrict__ te,
                                              const int *__restrict__ ptr, const int64_t *__restrict__ ss,
                                              const int64_t *__restrict__ se, const PN *__restrict__ pn,
                                              const double2 *__restrict__ dens, double2 *__restrict__ res, double k)
 {
+    using C = typename Cx<R>::T;
     const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (leaf >= n_leaf) return;
     const int lane = threadIdx.x & 63;
-    const double ik = 1.0 / k;
+    const R kr = (R)k, ik = (R)(1.0 / k);
     const int64_t t0 = ts[leaf], t1 = te[leaf];
     const int e0 = ptr[leaf], e1 = ptr[leaf + 1];
     for (int64_t ib = t0; ib < t1; ib += 64) {
@@ -193,16 +225,17 @@ __global__ __launch_bounds__(256) void k_p2p(int n_leaf, const int64_t *__restri
         const bool act = t < nt;
         const int64_t i = ib + (act ? t : 0);
         const PN X = pn[i];
-        double2 acc = make_double2(0.0, 0.0);
+        C acc = Cx<R>::mk(0, 0);
         if (act) {
             for (int e = e0; e < e1; ++e) {
                 const int64_t s1 = se[e];
                 for (int64_t j = ss[e] + q; j < s1; j += S) {
                     if (j == i) continue;
                     const PN Y = pn[j];
-                    const double2 K = kernel_op<OPK>(X.x - Y.x, X.y - Y.y, X.z - Y.z, X.nx, X.ny, X.nz, Y.nx, Y.ny,
-                                                     Y.nz, k, ik);
-                    acc = cadd(acc, cmul(K, dens[j]));
+                    // the difference in FP64 keeps the phase accurate; the kernel runs in R
+                    const C K = kernel_op<OPK, R>((R)(X.x - Y.x), (R)(X.y - Y.y), (R)(X.z - Y.z), (R)X.nx, (R)X.ny,
+                                                  (R)X.nz, (R)Y.nx, (R)Y.ny, (R)Y.nz, kr, ik);
+                    acc = cadd(acc, cmul(K, from64<C>(dens[j])));
                 }
             }
         }
@@ -210,86 +243,96 @@ __global__ __launch_bounds__(256) void k_p2p(int n_leaf, const int64_t *__restri
             acc.x += __shfl_xor(acc.x, off);
             acc.y += __shfl_xor(acc.y, off);
         }
-        if (act && q == 0) res[ib + t] = acc;
+        if (act && q == 0) res[ib + t] = to64(acc);
     }
 }
 
 // S2M: check potentials of the leaf's sources at the level's check points
 // (template + leaf centre), then x = W phi written to the outgoing slot.
 constexpr int LEAF_BLOCK = 256;
+template <typename R, typename O>
 __global__ __launch_bounds__(LEAF_BLOCK) void k_s2m(const int64_t *__restrict__ start, const int64_t *__restrict__ end,
                                                     const int64_t *__restrict__ slot, const int *__restrict__ tmpl,
                                                     const double *__restrict__ center, const int *__restrict__ t_s,
                                                     const int *__restrict__ t_ny, const int64_t *__restrict__ t_yoff,
                                                     const int64_t *__restrict__ t_woff, const double *__restrict__ tY,
-                                                    const double2 *__restrict__ tW, const double *__restrict__ X,
-                                                    const double *__restrict__ Y, const double *__restrict__ Z,
-                                                    const double *__restrict__ NX, const double *__restrict__ NY,
-                                                    const double *__restrict__ NZ, const double2 *__restrict__ dens,
-                                                    double2 *__restrict__ od, double k, OpC c)
+                                                    const typename Cx<R>::T *__restrict__ tW,
+                                                    const double *__restrict__ X, const double *__restrict__ Y,
+                                                    const double *__restrict__ Z, const double *__restrict__ NX,
+                                                    const double *__restrict__ NY, const double *__restrict__ NZ,
+                                                    const double2 *__restrict__ dens,
+                                                    typename Cx<R>::T *__restrict__ od, double k, O c)
 {
-    extern __shared__ double2 phi[];
+    using C = typename Cx<R>::T;
+    extern __shared__ unsigned char shraw[];
+    C *phi = (C *)shraw;
     const int task = blockIdx.x, tid = threadIdx.x;
     const int lev = tmpl[task];
     const int s = t_s[lev], ny = t_ny[lev];
     const double *Yt = tY + t_yoff[lev];
-    const double2 *W = tW + t_woff[lev];
+    const C *W = tW + t_woff[lev];
     const double cx = center[3 * task], cy = center[3 * task + 1], cz = center[3 * task + 2];
     const int64_t j0 = start[task], j1 = end[task];
     for (int a = tid; a < ny; a += LEAF_BLOCK) {
         const double ax = cx + Yt[3 * a], ay = cy + Yt[3 * a + 1], az = cz + Yt[3 * a + 2];
-        double2 acc = make_double2(0.0, 0.0);
+        C acc = Cx<R>::mk(0, 0);
         for (int64_t j = j0; j < j1; ++j) {
-            const double2 K = kernel_src(ax - X[j], ay - Y[j], az - Z[j], NX[j], NY[j], NZ[j], k, c);
-            acc = cadd(acc, cmul(K, dens[j]));
+            const C K = kernel_src<R>((R)(ax - X[j]), (R)(ay - Y[j]), (R)(az - Z[j]), (R)NX[j], (R)NY[j], (R)NZ[j],
+                                      (R)k, c);
+            acc = cadd(acc, cmul(K, from64<C>(dens[j])));
         }
         phi[a] = acc;
     }
     __syncthreads();
     const int64_t so = slot[task];
     for (int r = tid; r < s; r += LEAF_BLOCK) {
-        double2 acc = make_double2(0.0, 0.0);
+        C acc = Cx<R>::mk(0, 0);
         for (int a = 0; a < ny; ++a) acc = cadd(acc, cmul(W[r + (int64_t)a * s], phi[a]));
         od[so + r] = cadd(od[so + r], acc);
     }
 }
 
 // L2T: incoming equivalent densities q = W^T y, then E_dn q at the targets.
+template <typename R, typename O>
 __global__ __launch_bounds__(LEAF_BLOCK) void k_l2t(const int64_t *__restrict__ start, const int64_t *__restrict__ end,
                                                     const int64_t *__restrict__ slot, const int *__restrict__ tmpl,
                                                     const double *__restrict__ center, const int *__restrict__ t_s,
                                                     const int *__restrict__ t_ny, const int64_t *__restrict__ t_yoff,
                                                     const int64_t *__restrict__ t_woff, const double *__restrict__ tY,
-                                                    const double2 *__restrict__ tW, const double *__restrict__ X,
-                                                    const double *__restrict__ Y, const double *__restrict__ Z,
-                                                    const double *__restrict__ NX, const double *__restrict__ NY,
-                                                    const double *__restrict__ NZ, const double2 *__restrict__ id,
-                                                    double2 *__restrict__ res, double k, OpC c)
+                                                    const typename Cx<R>::T *__restrict__ tW,
+                                                    const double *__restrict__ X, const double *__restrict__ Y,
+                                                    const double *__restrict__ Z, const double *__restrict__ NX,
+                                                    const double *__restrict__ NY, const double *__restrict__ NZ,
+                                                    const typename Cx<R>::T *__restrict__ id,
+                                                    double2 *__restrict__ res, double k, O c)
 {
-    extern __shared__ double2 q[];
+    using C = typename Cx<R>::T;
+    extern __shared__ unsigned char shraw[];
+    C *q = (C *)shraw;
     const int task = blockIdx.x, tid = threadIdx.x;
     const int lev = tmpl[task];
     const int s = t_s[lev], ny = t_ny[lev];
     const double *Yt = tY + t_yoff[lev];
-    const double2 *W = tW + t_woff[lev];
+    const C *W = tW + t_woff[lev];
     const double cx = center[3 * task], cy = center[3 * task + 1], cz = center[3 * task + 2];
     const int64_t so = slot[task];
     for (int a = tid; a < ny; a += LEAF_BLOCK) {
-        double2 acc = make_double2(0.0, 0.0);
+        C acc = Cx<R>::mk(0, 0);
         for (int r = 0; r < s; ++r) acc = cadd(acc, cmul(W[r + (int64_t)a * s], id[so + r]));
         q[a] = acc;
     }
     __syncthreads();
     const int64_t i0 = start[task], i1 = end[task];
     for (int64_t i = i0 + tid; i < i1; i += LEAF_BLOCK) {
-        const double xi = X[i], yi = Y[i], zi = Z[i], nxi = NX[i], nyi = NY[i], nzi = NZ[i];
-        double2 acc = make_double2(0.0, 0.0);
+        const double xi = X[i], yi = Y[i], zi = Z[i];
+        const R nxi = (R)NX[i], nyi = (R)NY[i], nzi = (R)NZ[i];
+        C acc = Cx<R>::mk(0, 0);
         for (int a = 0; a < ny; ++a) {
-            const double2 K =
-                kernel_tgt(xi - (cx + Yt[3 * a]), yi - (cy + Yt[3 * a + 1]), zi - (cz + Yt[3 * a + 2]), nxi, nyi, nzi, k, c);
+            const C K = kernel_tgt<R>((R)(xi - (cx + Yt[3 * a])), (R)(yi - (cy + Yt[3 * a + 1])),
+                                      (R)(zi - (cz + Yt[3 * a + 2])), nxi, nyi, nzi, (R)k, c);
             acc = cadd(acc, cmul(K, q[a]));
         }
-        res[i] = cadd(res[i], acc);
+        res[i] = cadd(res[i], to64(acc));
     }
 }
 
@@ -494,58 +537,61 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int TAG, bool TRANS>
+template <int TAG, bool TRANS, typename R>
 __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks(int n_chunks, int s, int cols, int rmax,
-                                                                const int64_t *__restrict__ ch_mat,
-                                                                const int *__restrict__ ch_rank,
-                                                                const int *__restrict__ ch_pptr,
-                                                                const int64_t *__restrict__ pr_tgt,
-                                                                const int64_t *__restrict__ pr_src,
-                                                                const double2 *__restrict__ mat,
-                                                                const double2 *__restrict__ od, double2 *id)
+                                                            const int64_t *__restrict__ ch_mat,
+                                                            const int *__restrict__ ch_rank,
+                                                            const int *__restrict__ ch_pptr,
+                                                            const int64_t *__restrict__ pr_tgt,
+                                                            const int64_t *__restrict__ pr_src,
+                                                            const typename Cx<R>::T *__restrict__ mat,
+                                                            const typename Cx<R>::T *__restrict__ od,
+                                                            typename Cx<R>::T *id)
 {
-    extern __shared__ double2 sh[];
+    using C = typename Cx<R>::T;
+    extern __shared__ unsigned char shraw[];
+    C *sh = (C *)shraw;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * M2LC_WAVES + wv;
     if (c >= n_chunks) return;
     // s: output rows, cols: input length (both equal for M2L)
-    double2 *X = sh + (size_t)wv * (M2LC_CH * cols + M2LC_CH * rmax);
-    double2 *T = X + M2LC_CH * cols;
+    C *X = sh + (size_t)wv * (M2LC_CH * cols + M2LC_CH * rmax);
+    C *T = X + M2LC_CH * cols;
     const int p0 = ch_pptr[c], n = ch_pptr[c + 1] - p0;
     for (int i = lane; i < n * cols; i += 64) {
         const int p = i / cols, j = i - p * cols;
         X[p * cols + j] = od[pr_src[p0 + p] + j];
     }
     wave_sync();
-    const double2 *M = mat + ch_mat[c];
+    const C *M = mat + ch_mat[c];
     const int r = ch_rank[c];
-    double2 acc[M2LC_CH];
+    C acc[M2LC_CH];
     if (r >= 0) {
         // t = V x for every (rank index, pair) item of the chunk
-        const double2 *V = M + (size_t)s * r;
+        const C *V = M + (size_t)s * r;
         for (int it = lane; it < r * n; it += 64) {
             const int p = it / r, qq = it - p * r;
-            const double2 *xp = X + p * s;
-            double2 a = make_double2(0.0, 0.0);
-            for (int j = 0; j < s; ++j) a = cadd(a, cmul(V[qq + (size_t)j * r], xp[j]));
+            const C *xp = X + p * cols;
+            C a = Cx<R>::mk(0, 0);
+            for (int j = 0; j < cols; ++j) a = cadd(a, cmul(V[qq + (size_t)j * r], xp[j]));
             T[p * rmax + qq] = a;
         }
         wave_sync();
     }
     for (int row = lane; row < s; row += 64) {
 #pragma unroll
-        for (int p = 0; p < M2LC_CH; ++p) acc[p] = make_double2(0.0, 0.0);
+        for (int p = 0; p < M2LC_CH; ++p) acc[p] = Cx<R>::mk(0, 0);
         if (r < 0) {
             for (int j = 0; j < cols; ++j) {
                 // dense operator s x cols, or its transpose stored cols x s
-                const double2 m = TRANS ? M[j + (size_t)row * cols] : M[row + (size_t)j * s];
+                const C m = TRANS ? M[j + (size_t)row * cols] : M[row + (size_t)j * s];
 #pragma unroll
                 for (int p = 0; p < M2LC_CH; ++p)
                     if (p < n) acc[p] = cadd(acc[p], cmul(m, X[p * cols + j]));
             }
         } else {
             for (int qq = 0; qq < r; ++qq) {
-                const double2 m = M[row + (size_t)qq * s];
+                const C m = M[row + (size_t)qq * s];
 #pragma unroll
                 for (int p = 0; p < M2LC_CH; ++p)
                     if (p < n) acc[p] = cadd(acc[p], cmul(m, T[p * rmax + qq]));
@@ -554,7 +600,7 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks(int n_chunks, int s,
 #pragma unroll
         for (int p = 0; p < M2LC_CH; ++p)
             if (p < n) {
-                double *o = (double *)(id + pr_tgt[p0 + p] + row);
+                R *o = (R *)(id + pr_tgt[p0 + p] + row);
                 atomicAdd(o, acc[p].x);
                 atomicAdd(o + 1, acc[p].y);
             }
@@ -770,7 +816,7 @@ void device_upload(Plan &P)
                                         (int64_t)P.m2l_chunks[l].pr_tgt.size(), 0});
                 if (D.m2lc[l].shm > (size_t)maxsh) D.m2l_mode = 1;
                 if (D.m2lc[l].shm > 65536)
-                    HIP_CHECK(hipFuncSetAttribute((const void *)k_chunks<TAG_M2L, false>,
+                    HIP_CHECK(hipFuncSetAttribute((const void *)k_chunks<TAG_M2L, false, double>,
                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)D.m2lc[l].shm));
             }
             P.m2l_chunks.clear();
@@ -846,8 +892,23 @@ void device_upload(Plan &P)
         D.l2t = upload_leaf(D, P, P.l2t_tasks);
         D.n_od = P.out_total;
         D.n_id = P.in_total;
-        D.od = dalloc<double2>(D, D.n_od);
-        D.id = dalloc<double2>(D, D.n_id);
+        D.prec = P.opt.precision;
+        if (D.prec >= 1) {
+            if (D.m2l_mode != 0) throw std::runtime_error("FP32 far field needs the operator-chunk M2L schedule");
+            std::vector<float2> mf(P.matpool.size()), wf;
+            for (size_t i = 0; i < mf.size(); ++i)
+                mf[i] = make_float2((float)P.matpool[i].real(), (float)P.matpool[i].imag());
+            D.matf = dupload(D, mf);
+            for (int l = 0; l < nlev; ++l)
+                for (const cplx &v : P.tmpl[l].W.a) wf.push_back(make_float2((float)v.real(), (float)v.imag()));
+            D.t_Wf = dupload(D, wf);
+            D.odf = dalloc<float2>(D, D.n_od);
+            D.idf = dalloc<float2>(D, D.n_id);
+        }
+        if (D.prec != 1) {
+            D.od = dalloc<double2>(D, D.n_od);
+            D.id = dalloc<double2>(D, D.n_id);
+        }
     }
     D.dens = dalloc<double2>(D, P.N);
     D.res = dalloc<double2>(D, P.N);
@@ -911,59 +972,97 @@ static void run_gemv(const DGemv &g, const double2 *mat, const double2 *in, doub
                        g.rows, g.cols, g.trans, mat, in, out);
 }
 
+template <typename R, typename O>
+static void launch_p2p(Plan &P, Device &D, int op, hipStream_t st)
+{
+    const int opk = (op == 0 || op == 3) ? OPK_H : (op == 1 || op == 4) ? OPK_G : OPK_T1;
+    const dim3 g((D.n_leaf + 3) / 4), b(256);
+    if (opk == OPK_H)
+        hipLaunchKernelGGL((k_p2p<OPK_H, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
+                           (const PN *)D.pn, D.dens, D.res, P.k);
+    else if (opk == OPK_G)
+        hipLaunchKernelGGL((k_p2p<OPK_G, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
+                           (const PN *)D.pn, D.dens, D.res, P.k);
+    else
+        hipLaunchKernelGGL((k_p2p<OPK_T1, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss,
+                           D.p2p_se, (const PN *)D.pn, D.dens, D.res, P.k);
+}
+
+template <int TAG, bool TRANS, typename R>
+static void launch_chunks(const DChunks &C, int cols, const typename Cx<R>::T *mat, const typename Cx<R>::T *in,
+                          typename Cx<R>::T *out, hipStream_t st)
+{
+    if (!C.n) return;
+    const size_t shm = C.shm * sizeof(typename Cx<R>::T) / sizeof(double2);
+    hipLaunchKernelGGL((k_chunks<TAG, TRANS, R>), dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES), dim3(64 * M2LC_WAVES),
+                       shm, st, C.n, C.s, cols, C.rmax, C.ch_mat, C.ch_rank, C.ch_pptr, C.pr_tgt, C.pr_src, mat, in,
+                       out);
+}
+
+// S2M .. L2T in working precision R (operator-chunk schedule)
+template <typename R, typename O>
+static void far_field_chunks(Plan &P, Device &D, const O &c, const typename Cx<R>::T *mat, const typename Cx<R>::T *tW,
+                             typename Cx<R>::T *od, typename Cx<R>::T *id, hipEvent_t *ev, hipStream_t st)
+{
+    using C = typename Cx<R>::T;
+    if (D.n_od) hipLaunchKernelGGL(k_fill_zero<C>, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, od, D.n_od);
+    if (D.n_id) hipLaunchKernelGGL(k_fill_zero<C>, dim3(nblk(D.n_id, 256)), dim3(256), 0, st, id, D.n_id);
+    const size_t shm_leaf = sizeof(C) * std::max(P.max_Y_leaf, 1);
+    if (D.s2m.n)
+        hipLaunchKernelGGL((k_s2m<R, O>), dim3(D.s2m.n), dim3(LEAF_BLOCK), shm_leaf, st, D.s2m.start, D.s2m.end,
+                           D.s2m.slot, D.s2m.tmpl, D.s2m.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, tW, D.x,
+                           D.y, D.z, D.nx, D.ny, D.nz, D.dens, od, P.k, c);
+    if (ev) HIP_CHECK(hipEventRecord(ev[3], st));
+    for (int l = D.n_lev - 2; l >= 0; --l) launch_chunks<TAG_M2M, false, R>(D.m2mc[l], D.m2mc[l].cols, mat, od, od, st);
+    if (ev) HIP_CHECK(hipEventRecord(ev[4], st));
+    for (int l = 0; l < D.n_lev; ++l) launch_chunks<TAG_M2L, false, R>(D.m2lc[l], D.m2lc[l].s, mat, od, id, st);
+    if (ev) HIP_CHECK(hipEventRecord(ev[5], st));
+    for (int l = 1; l < D.n_lev; ++l) launch_chunks<TAG_L2L, true, R>(D.l2lc[l], D.l2lc[l].cols, mat, id, id, st);
+    if (ev) HIP_CHECK(hipEventRecord(ev[6], st));
+    if (D.l2t.n)
+        hipLaunchKernelGGL((k_l2t<R, O>), dim3(D.l2t.n), dim3(LEAF_BLOCK), shm_leaf, st, D.l2t.start, D.l2t.end,
+                           D.l2t.slot, D.l2t.tmpl, D.l2t.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, tW, D.x,
+                           D.y, D.z, D.nx, D.ny, D.nz, id, D.res, P.k, c);
+}
+
 void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st)
 {
     Device &D = *P.dev;
     const int64_t N = P.N;
+    // low byte: operator; FDA_OP_FP32 (0x100) selects the FP32 far field and
+    // near field on plans built with both precisions
+    const bool f32 = D.prec == 1 || (D.prec == 2 && (op & 0x100));
+    op &= 0xff;
     const OpC c = op_coef(op, P.k);
-    const bool bm = (op == 3 || op == 4);
     const bool tm = D.timing != 0;
     hipEvent_t *ev = tm ? &D.ev[(size_t)(D.ring_pos % Device::kRing) * 10] : nullptr;
     if (tm) HIP_CHECK(hipEventRecord(ev[0], st));
     hipLaunchKernelGGL(k_permute_in, dim3(nblk(N, 256)), dim3(256), 0, st, in, D.perm, D.w, D.dens, N);
     if (tm) HIP_CHECK(hipEventRecord(ev[1], st));
-    {
-        const int opk = (op == 0 || op == 3) ? OPK_H : (op == 1 || op == 4) ? OPK_G : OPK_T1;
-        const dim3 g((D.n_leaf + 3) / 4), b(256);
-        if (opk == OPK_H)
-            hipLaunchKernelGGL(k_p2p<OPK_H>, g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
-                               (const PN *)D.pn, D.dens, D.res, P.k);
-        else if (opk == OPK_G)
-            hipLaunchKernelGGL(k_p2p<OPK_G>, g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
-                               (const PN *)D.pn, D.dens, D.res, P.k);
-        else
-            hipLaunchKernelGGL(k_p2p<OPK_T1>, g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
-                               (const PN *)D.pn, D.dens, D.res, P.k);
-    }
+    if (f32)
+        launch_p2p<float, OpCf>(P, D, op, st);
+    else
+        launch_p2p<double, OpC>(P, D, op, st);
     if (tm) HIP_CHECK(hipEventRecord(ev[2], st));
-    if (P.opt.far_field) {
-        if (D.n_od) hipLaunchKernelGGL(k_fill_zero, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, D.od, D.n_od);
-        if (D.n_id) hipLaunchKernelGGL(k_fill_zero, dim3(nblk(D.n_id, 256)), dim3(256), 0, st, D.id, D.n_id);
+    if (P.opt.far_field && f32) {
+        const OpCf cf = {make_float2((float)c.c0.x, (float)c.c0.y), make_float2((float)c.c1.x, (float)c.c1.y),
+                         make_float2((float)c.d0.x, (float)c.d0.y), make_float2((float)c.d1.x, (float)c.d1.y)};
+        far_field_chunks<float, OpCf>(P, D, cf, D.matf, D.t_Wf, D.odf, D.idf, ev, st);
+    } else if (P.opt.far_field && D.m2l_mode == 0) {
+        far_field_chunks<double, OpC>(P, D, c, D.mat, D.t_W, D.od, D.id, ev, st);
+    } else if (P.opt.far_field) {
+        if (D.n_od) hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, D.od, D.n_od);
+        if (D.n_id) hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_id, 256)), dim3(256), 0, st, D.id, D.n_id);
         const size_t shm_leaf = sizeof(double2) * std::max(P.max_Y_leaf, 1);
         if (D.s2m.n)
-            hipLaunchKernelGGL(k_s2m, dim3(D.s2m.n), dim3(LEAF_BLOCK), shm_leaf, st, D.s2m.start, D.s2m.end,
-                               D.s2m.slot, D.s2m.tmpl, D.s2m.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, D.t_W,
-                               D.x, D.y, D.z, D.nx, D.ny, D.nz, D.dens, D.od, P.k, c);
+            hipLaunchKernelGGL((k_s2m<double, OpC>), dim3(D.s2m.n), dim3(LEAF_BLOCK), shm_leaf, st, D.s2m.start,
+                               D.s2m.end, D.s2m.slot, D.s2m.tmpl, D.s2m.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff,
+                               D.t_Y, D.t_W, D.x, D.y, D.z, D.nx, D.ny, D.nz, D.dens, D.od, P.k, c);
         if (tm) HIP_CHECK(hipEventRecord(ev[3], st));
-        for (int l = D.n_lev - 2; l >= 0; --l) {
-            if (D.m2l_mode == 0) {
-                const DChunks &C = D.m2mc[l];
-                if (C.n)
-                    hipLaunchKernelGGL((k_chunks<TAG_M2M, false>), dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES),
-                                       dim3(64 * M2LC_WAVES), C.shm, st, C.n, C.s, C.cols, C.rmax, C.ch_mat, C.ch_rank,
-                                       C.ch_pptr, C.pr_tgt, C.pr_src, D.mat, D.od, D.od);
-            } else
-                run_gemv<TAG_M2M>(D.m2m[l], D.mat, D.od, D.od, st);
-        }
+        for (int l = D.n_lev - 2; l >= 0; --l) run_gemv<TAG_M2M>(D.m2m[l], D.mat, D.od, D.od, st);
         if (tm) HIP_CHECK(hipEventRecord(ev[4], st));
         for (int l = 0; l < D.n_lev; ++l) {
-            if (D.m2l_mode == 0) {
-                const DChunks &C = D.m2lc[l];
-                if (C.n)
-                    hipLaunchKernelGGL((k_chunks<TAG_M2L, false>), dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES),
-                                       dim3(64 * M2LC_WAVES), C.shm, st, C.n, C.s, C.s, C.rmax, C.ch_mat, C.ch_rank,
-                                       C.ch_pptr, C.pr_tgt, C.pr_src, D.mat, D.od, D.id);
-            } else if (D.m2l_mode == 2) {
+            if (D.m2l_mode == 2) {
                 const DTiles &T = D.m2lt[l];
                 if (T.n_tiles) {
                     hipLaunchKernelGGL(k_m2l_tile, dim3(T.n_tiles * T.nseg), dim3(M2L_BLOCK), T.shm, st, T.s, T.rmax,
@@ -977,27 +1076,19 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
                 run_gemv<TAG_M2L>(D.m2l[l], D.mat, D.od, D.id, st);
         }
         if (tm) HIP_CHECK(hipEventRecord(ev[5], st));
-        for (int l = 1; l < D.n_lev; ++l) {
-            if (D.m2l_mode == 0) {
-                const DChunks &C = D.l2lc[l];
-                if (C.n)
-                    hipLaunchKernelGGL((k_chunks<TAG_L2L, true>), dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES),
-                                       dim3(64 * M2LC_WAVES), C.shm, st, C.n, C.s, C.cols, C.rmax, C.ch_mat, C.ch_rank,
-                                       C.ch_pptr, C.pr_tgt, C.pr_src, D.mat, D.id, D.id);
-            } else
-                run_gemv<TAG_L2L>(D.l2l[l], D.mat, D.id, D.id, st);
-        }
+        for (int l = 1; l < D.n_lev; ++l) run_gemv<TAG_L2L>(D.l2l[l], D.mat, D.id, D.id, st);
         if (tm) HIP_CHECK(hipEventRecord(ev[6], st));
         if (D.l2t.n)
-            hipLaunchKernelGGL(k_l2t, dim3(D.l2t.n), dim3(LEAF_BLOCK), shm_leaf, st, D.l2t.start, D.l2t.end,
-                               D.l2t.slot, D.l2t.tmpl, D.l2t.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, D.t_W,
-                               D.x, D.y, D.z, D.nx, D.ny, D.nz, D.id, D.res, P.k, c);
+            hipLaunchKernelGGL((k_l2t<double, OpC>), dim3(D.l2t.n), dim3(LEAF_BLOCK), shm_leaf, st, D.l2t.start,
+                               D.l2t.end, D.l2t.slot, D.l2t.tmpl, D.l2t.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff,
+                               D.t_Y, D.t_W, D.x, D.y, D.z, D.nx, D.ny, D.nz, D.id, D.res, P.k, c);
     } else if (tm) {
         for (int e = 3; e <= 6; ++e) HIP_CHECK(hipEventRecord(ev[e], st));
     }
     if (tm) HIP_CHECK(hipEventRecord(ev[7], st));
     hipLaunchKernelGGL(k_permute_out, dim3(nblk(N, 256)), dim3(256), 0, st, D.res, D.perm, in, op == 3 ? 0.5 : 0.0, out, N);
     if (tm) HIP_CHECK(hipEventRecord(ev[8], st));
+    // the near-field correction stays in FP64 in both precisions
     if (op == 3 && D.corr.val)
         hipLaunchKernelGGL(k_corr, dim3(nblk(N, 256)), dim3(256), 0, st, D.corr.rp, D.corr.blk, D.corr.val, in, out, N);
     if (op == 4 && D.corrg.val)

@@ -77,6 +77,8 @@ struct Device {
     double2 *dens = nullptr;     // weighted sorted density (N)
     double2 *res = nullptr;      // sorted result (N)
     double2 *od = nullptr, *id = nullptr;
+    int prec = 0;                // 0 FP64, 1 FP32 far field and P2P
+    float2 *matf = nullptr, *t_Wf = nullptr, *odf = nullptr, *idf = nullptr;
     int64_t n_od = 0, n_id = 0;
     // near-field corrections (caller order, block CSR: 6 columns per element)
     DCorr corr, corrg;

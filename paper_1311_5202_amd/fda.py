@@ -76,6 +76,8 @@ class Plan:
                              0 if el is None else el.shape[0], None if el is None else el.ctypes.data)
         o = _abi.FdaOpts()
         _abi.check(L.fda_default_opts(ctypes.byref(o)))
+        if isinstance(opts.get("precision"), str):
+            opts["precision"] = _abi.PREC[opts["precision"]]
         for key, val in opts.items():
             if not hasattr(o, key):
                 raise TypeError(f"unknown option {key}")
@@ -95,14 +97,18 @@ class Plan:
         except Exception:
             pass
 
-    def matvec(self, u, op: str = "RAW_H", out=None, stream=None):
+    @staticmethod
+    def _op(op: str, fp32: bool) -> int:
+        return _abi.OPS[op] | (_abi.FDA_OP_FP32 if fp32 else 0)
+
+    def matvec(self, u, op: str = "RAW_H", out=None, stream=None, fp32: bool = False):
         import torch
 
         _check_vec(u, self.n)
         if out is None:
             out = torch.empty_like(u)
         _check_vec(out, self.n)
-        _abi.check(_abi.lib().fda_matvec(self._h, _abi.OPS[op], ctypes.c_void_p(u.data_ptr()),
+        _abi.check(_abi.lib().fda_matvec(self._h, self._op(op, fp32), ctypes.c_void_p(u.data_ptr()),
                                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
@@ -115,7 +121,7 @@ class Plan:
         return out
 
     def solve(self, rhs, tol: float, maxit: int = 200, restart: int = 200, op: str = "BM_H", precond: int = 0,
-              stream=None, raise_on_fail: bool = True):
+              stream=None, raise_on_fail: bool = True, fp32: bool = False):
         import torch
 
         _check_vec(rhs, self.n)
@@ -123,7 +129,7 @@ class Plan:
         it = ctypes.c_int(0)
         rel = ctypes.c_double(0)
         hist = np.zeros(maxit + 1)
-        rc = _abi.lib().bm_solve(self._h, _abi.OPS[op], ctypes.c_void_p(rhs.data_ptr()), float(tol), int(maxit),
+        rc = _abi.lib().bm_solve(self._h, self._op(op, fp32), ctypes.c_void_p(rhs.data_ptr()), float(tol), int(maxit),
                                  int(restart), int(precond), ctypes.c_void_p(x.data_ptr()), ctypes.byref(it),
                                  ctypes.byref(rel), hist.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream))
         info = {"status": rc, "iterations": it.value, "relres": rel.value, "history": hist[: it.value + 1].copy()}

@@ -115,3 +115,33 @@ def test_m2l_kernels_agree_and_tiles_are_deterministic(torch):
     ref = outs["gemv"]
     for name in ("chunks", "tiles"):
         assert np.max(np.abs(outs[name] - ref)) <= 1e-12 * np.max(np.abs(ref)), name
+
+
+def test_fp32_far_and_near_field(torch):
+    """FP32 point sums and far field (FDA_OP_FP32) on a plan holding both
+    precisions: within 1e-4 of the FP64 oracle; the difference to the FP64
+    path is reported."""
+    import paper_1311_5202_amd as fdb
+
+    _, pts, nrm, w = _geom(24)
+    k = 25.0
+    plan = fdb.build(pts, nrm, w, k, 1e-4, precision="both")
+    u = synth.random_densities(len(w), 4)
+    ud = torch.from_numpy(u).cuda()
+    rows = np.sort(np.random.default_rng(8).choice(len(w), 300, replace=False))
+    for op, oop in OPS:
+        g64 = plan.matvec(ud, op).cpu().numpy()
+        g32 = plan.matvec(ud, op, fp32=True).cpu().numpy()
+        ref = oracle.dense_rows(pts, nrm, w, u, k, oop, rows=rows)
+        e32 = oracle.rel_l2(g32[rows], ref)
+        d = oracle.rel_l2(g32, g64)
+        print(op, "fp32 vs oracle", e32, "fp32 vs fp64", d)
+        assert e32 <= 1e-4 and d <= 5e-5, op
+    plan.close()
+    # an FP64-only plan refuses the FP32 flag
+    from paper_1311_5202_amd import _abi
+
+    plan = fdb.build(pts[:600], nrm[:600], w[:600], k, 1e-4)
+    with pytest.raises(_abi.FdaError):
+        plan.matvec(torch.from_numpy(u[:600]).cuda(), "RAW_H", fp32=True)
+    plan.close()

@@ -105,3 +105,21 @@ def test_gmres_reports_nonconvergence_and_nonfinite(torch):
     with pytest.raises(_abi.FdaError):
         plan.solve(b, 1e-6, maxit=5)
     plan.close()
+
+
+def test_fp32_solve_matches_fp64(torch):
+    """GMRES to 1e-4 with the FP32 operator (FP64 Arnoldi and corrections)
+    reaches the FP64 solution to the solver tolerance."""
+    import paper_1311_5202_amd as fdb
+
+    k = 5.0
+    el = synth.octa_sphere(8)
+    pts, nrm, w = fdb.nystrom_nodes(el)
+    plan = fdb.build(pts, nrm, w, k, 1e-4, elements=el, precision="both")
+    b = plan.rhs_plane_wave((0.0, 0.0, 1.0))
+    x64, i64 = plan.solve(b, 1e-6)
+    x32, i32 = plan.solve(b, 1e-4, fp32=True)
+    d = oracle.rel_l2(x32.cpu().numpy(), x64.cpu().numpy())
+    print("iterations fp64", i64["iterations"], "fp32", i32["iterations"], "difference", d)
+    assert i32["status"] == 0 and d < 5e-4
+    plan.close()
