@@ -134,7 +134,9 @@ int fda_matvec(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *
  * re-orthogonalisation, FP64).  Stops when ||b - A x|| / ||b|| <= tol.
  * rhs_dev/x_dev: complex128[N] device buffers.  iters_out, relres_out may be
  * NULL; resid_hist (host, maxit+1 doubles) may be NULL.  precond: 0 none,
- * 1 block-Jacobi on the corrected near-field leaf blocks.  Synchronises the
+ * 1 block-Jacobi on the corrected near-field leaf blocks, 2 block-Jacobi plus
+ * the learned coupling loaded by fda_net_attach, 3 the restricted additive
+ * Schwarz rows R_b that the coupling is trained towards (see fda_net_*).  Synchronises the
  * stream once per iteration.  FDA_NOT_CONVERGED leaves the last iterate. */
 int bm_solve(fda_plan *plan, int op, const void *rhs_dev, double tol, int maxit, int restart, int precond,
              void *x_dev, int *iters_out, double *relres_out, double *resid_hist, void *hip_stream);
@@ -158,6 +160,53 @@ int fda_set_timing(fda_plan *plan, int on);
  * L2T, near correction, permutations; n: capacity of ms.  Waits for the
  * recorded events, then starts a new averaging window. */
 int fda_phase_times(fda_plan *plan, double *ms, int n);
+
+/* ---- learned coupling correction of the block-Jacobi preconditioner ----
+ * Not part of the paper's method: a preconditioner for bm_solve.  Blocks b
+ * are the octree leaves cut into pieces of at most 64 points; E_b is the block
+ * followed by up to 64 of its nearest points among the leaf's direct-sum
+ * sources (ne_b <= 128).  With precond = 2 bm_solve applies
+ *   z_b = A_bb^{-1} v_b + U_b (W_b^H v_{E_b}),
+ * A_bb the corrected near-field block of BM_H, U_b (n_b x 4) and W_b
+ * (ne_b x 4) produced row by row by a small network (12 features of the pair
+ * (b, j) -> 32 tanh -> 16 outputs: Re/Im of row j of U, then of W).
+ * Training target: the restricted additive Schwarz rows R_b =
+ * [(A|E_b)^{-1}]_{b,E_b}; loss = sum_b w_b ||[A_bb^{-1} 0] + U_b W_b^H -
+ * R_b||_F^2 with w_b = 1/||R_b - [A_bb^{-1} 0]||_F^2 (0 when that is at most
+ * 1e-12 ||R_b||_F^2).  Features, forward, backward and Adam run on the GPU;
+ * the network lives on the device current at fda_net_create.  Every call is
+ * synchronous. */
+typedef struct fda_net fda_net;
+
+int fda_net_num_params(void);
+int fda_net_create(uint64_t seed, fda_net **out);
+void fda_net_destroy(fda_net *net);
+/* parameters: host arrays of fda_net_num_params() doubles, laid out as W1
+ * (32 x 12 row-major), b1 (32), W2 (16 x 32 row-major), b2 (16) */
+int fda_net_get_params(const fda_net *net, double *params);
+int fda_net_set_params(fda_net *net, const double *params);  /* FDA_EINVAL on non-finite values */
+/* loss and gradient (host array, may be NULL) over the plan's blocks.  Builds
+ * the plan's overlapping sets and targets on first use (the plan needs
+ * elements: FDA_EINVAL otherwise) and unloads factors loaded by
+ * fda_net_attach (load them again before precond = 2). */
+int fda_net_loss_grad(fda_net *net, fda_plan *plan, double *loss, double *grad);
+/* one Adam step (beta 0.9, 0.999) of learning rate lr > 0 on the plan's
+ * blocks; *loss (may be NULL) is the loss before the step */
+int fda_net_train_step(fda_net *net, fda_plan *plan, double lr, double *loss);
+/* evaluate the network on the plan and load the factors for precond = 2;
+ * net = NULL unloads them (precond = 2 then reports FDA_ENOTSUP) */
+int fda_net_attach(fda_net *net, fda_plan *plan);
+/* loss and gradient for caller data, all device pointers: per block b,
+ * feature rows [pair_off[b], pair_off[b] + block_ne[b]) of the n_rows x 12
+ * array (block points first), the inverse block at inv_off[b] (n_b x n_b) and
+ * the target at target_off[b] (n_b x ne_b), column-major complex128.
+ * FDA_EINVAL unless 1 <= n_b <= 64, n_b <= ne_b <= 128 and the rows lie in
+ * the array; the complex arrays must hold the blocks at their offsets.  For
+ * checking the kernels against an independent implementation. */
+int fda_net_loss_grad_raw(fda_net *net, int n_blocks, const int64_t *pair_off, const int *block_n,
+                          const int *block_ne, const int64_t *inv_off, const int64_t *target_off, int64_t n_rows,
+                          const double *features, const void *block_inv, const void *targets, double *loss,
+                          double *grad);
 
 /* Release every device and host resource of the plan (NULL is allowed). */
 void fda_destroy(fda_plan *plan);

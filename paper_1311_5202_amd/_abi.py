@@ -22,7 +22,9 @@ FDA_OP_FP32 = 0x100
 PREC = {"fp64": 0, "fp32": 1, "both": 2}
 
 EXPORTS = ("fda_default_opts", "bem_nystrom_nodes", "bem_near_correction", "fda_build", "fda_matvec", "bm_solve", "fda_rhs_plane_wave",
-           "fda_stats", "fda_set_timing", "fda_phase_times", "fda_destroy", "fda_last_error")
+           "fda_stats", "fda_set_timing", "fda_phase_times", "fda_destroy", "fda_last_error", "fda_net_num_params",
+           "fda_net_create", "fda_net_destroy", "fda_net_get_params", "fda_net_set_params", "fda_net_loss_grad",
+           "fda_net_train_step", "fda_net_attach", "fda_net_loss_grad_raw")
 
 
 class FdaGeometry(ctypes.Structure):
@@ -66,11 +68,21 @@ def lib() -> ctypes.CDLL:
     L.fda_stats.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     L.fda_set_timing.argtypes = [vp, ci]
     L.fda_phase_times.argtypes = [vp, ctypes.POINTER(dbl), ci]
+    L.fda_net_num_params.argtypes = []
+    L.fda_net_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.fda_net_destroy.argtypes = [vp]
+    L.fda_net_destroy.restype = None
+    L.fda_net_get_params.argtypes = [vp, vp]
+    L.fda_net_set_params.argtypes = [vp, vp]
+    L.fda_net_loss_grad.argtypes = [vp, vp, ctypes.POINTER(dbl), vp]
+    L.fda_net_train_step.argtypes = [vp, vp, dbl, ctypes.POINTER(dbl)]
+    L.fda_net_attach.argtypes = [vp, vp]
+    L.fda_net_loss_grad_raw.argtypes = [vp, ci, vp, vp, vp, vp, vp, i64, vp, vp, vp, ctypes.POINTER(dbl), vp]
     L.fda_destroy.argtypes = [vp]
     L.fda_destroy.restype = None
     L.fda_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("fda_destroy", "fda_last_error"):
+        if name not in ("fda_destroy", "fda_last_error", "fda_net_destroy"):
             getattr(L, name).restype = ci
     _lib = L
     return L

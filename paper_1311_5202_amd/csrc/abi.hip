@@ -23,6 +23,10 @@ struct fda_plan {
     Plan *P;
 };
 
+struct fda_net {
+    LearnedNet *N;
+};
+
 static thread_local std::string g_err;
 
 static int fail(int code, const std::string &msg)
@@ -177,7 +181,7 @@ int bm_solve(fda_plan *plan, int op, const void *rhs_dev, double tol, int maxit,
         if (rc == FDA_NOT_CONVERGED) return fail(rc, "GMRES did not reach the tolerance");
         if (rc == FDA_NONFINITE) return fail(rc, "non-finite value in GMRES");
         if (rc == FDA_EBREAKDOWN) return fail(rc, "GMRES breakdown");
-        if (rc == FDA_ENOTSUP) return fail(rc, "preconditioner not available");
+        if (rc == FDA_ENOTSUP) return fail(rc, "preconditioner not available (1 and 3 need elements, 2 loaded factors)");
         return rc;
     });
 }
@@ -244,6 +248,105 @@ int fda_phase_times(fda_plan *plan, double *ms, int n)
         if (!plan || !ms || n < 0) throw std::invalid_argument("null argument");
         device_phase_average(*plan->P);
         for (int t = 0; t < n && t < 8; ++t) ms[t] = plan->P->dev->phase_ms[t];
+        return FDA_OK;
+    });
+}
+
+int fda_net_num_params(void) { return learned_num_params(); }
+
+int fda_net_create(uint64_t seed, fda_net **out)
+{
+    return guarded([&] {
+        if (!out) throw std::invalid_argument("null output pointer");
+        *out = new fda_net{learned_create(seed)};
+        return FDA_OK;
+    });
+}
+
+void fda_net_destroy(fda_net *net)
+{
+    if (!net) return;
+    try {
+        learned_destroy(net->N);
+    } catch (...) {
+    }
+    delete net;
+}
+
+int fda_net_get_params(const fda_net *net, double *params)
+{
+    return guarded([&] {
+        if (!net || !params) throw std::invalid_argument("null argument");
+        learned_get_params(net->N, params);
+        return FDA_OK;
+    });
+}
+
+int fda_net_set_params(fda_net *net, const double *params)
+{
+    return guarded([&] {
+        if (!net || !params) throw std::invalid_argument("null argument");
+        for (int i = 0; i < learned_num_params(); ++i)
+            if (!std::isfinite(params[i])) throw std::invalid_argument("non-finite network parameter");
+        learned_set_params(net->N, params);
+        return FDA_OK;
+    });
+}
+
+static void need_bm_plan(fda_plan *plan)
+{
+    if (!plan) throw std::invalid_argument("null plan");
+    if (!plan->P->has_corr) throw std::invalid_argument("the learned preconditioner needs a plan built with elements");
+}
+
+int fda_net_loss_grad(fda_net *net, fda_plan *plan, double *loss, double *grad)
+{
+    return guarded([&] {
+        if (!net || !loss) throw std::invalid_argument("null argument");
+        need_bm_plan(plan);
+        *loss = learned_loss_grad(net->N, *plan->P);
+        if (grad) learned_get_grad(net->N, grad);
+        return FDA_OK;
+    });
+}
+
+int fda_net_train_step(fda_net *net, fda_plan *plan, double lr, double *loss)
+{
+    return guarded([&] {
+        if (!net || !(lr > 0)) throw std::invalid_argument("bad argument");
+        need_bm_plan(plan);
+        const double l = learned_train_step(net->N, *plan->P, lr);
+        if (loss) *loss = l;
+        return FDA_OK;
+    });
+}
+
+int fda_net_attach(fda_net *net, fda_plan *plan)
+{
+    return guarded([&] {
+        need_bm_plan(plan);
+        if (!net) {
+            learned_detach(*plan->P);
+            return FDA_OK;
+        }
+        learned_attach(net->N, *plan->P);
+        return FDA_OK;
+    });
+}
+
+int fda_net_loss_grad_raw(fda_net *net, int n_blocks, const int64_t *pair_off, const int *block_n,
+                          const int *block_ne, const int64_t *inv_off, const int64_t *target_off, int64_t n_rows,
+                          const double *features, const void *block_inv, const void *targets, double *loss,
+                          double *grad)
+{
+    return guarded([&] {
+        if (!net || !pair_off || !block_n || !block_ne || !inv_off || !target_off || !features || !block_inv ||
+            !targets || !loss)
+            throw std::invalid_argument("null argument");
+        if (n_blocks <= 0 || n_rows <= 0) throw std::invalid_argument("empty problem");
+        *loss = learned_loss_grad_raw(net->N, n_blocks, pair_off, block_n, block_ne, inv_off, target_off, n_rows,
+                                      features, (const double2 *)block_inv, (const double2 *)targets);
+        if (grad) learned_get_grad(net->N, grad);
         return FDA_OK;
     });
 }

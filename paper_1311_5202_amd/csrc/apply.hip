@@ -931,7 +931,8 @@ void device_free(Plan &P)
     if (!P.dev) return;
     Device &D = *P.dev;
     for (void *p : D.allocs) (void)hipFree(p);
-    for (void *p : {(void *)D.gm_V, (void *)D.gm_w, (void *)D.gm_r, (void *)D.gm_h, (void *)D.gm_red_c})
+    for (void *p : {(void *)D.gm_V, (void *)D.gm_w, (void *)D.gm_r, (void *)D.gm_h, (void *)D.gm_red_c,
+                    (void *)D.gm_z, (void *)D.gm_t})
         if (p) (void)hipFree(p);
     for (auto &e : D.ev)
         if (e) (void)hipEventDestroy(e);

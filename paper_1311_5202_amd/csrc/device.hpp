@@ -40,6 +40,26 @@ struct DCorr {
     double2 *val = nullptr;   // per block: 6 complex weights
 };
 
+struct DBJ {
+    int n_blocks = 0, rank = 0;      // rank > 0: learned factors loaded
+    int64_t *start = nullptr, *off = nullptr;
+    int *size = nullptr;
+    double2 *inv = nullptr;          // inverted near-field blocks (column-major n x n at off)
+    // overlapping point sets E_b (block points first, caller indices) and the
+    // learned factor rows, one row per (block, point of E_b) pair
+    int *ne = nullptr;
+    int64_t *ext = nullptr;          // n_blocks x 128
+    int64_t *poff = nullptr;         // first pair row of each block
+    int64_t n_pairs = 0;
+    double *O = nullptr;             // network outputs per pair row
+};
+
+struct DLearn {
+    double2 *T = nullptr;            // targets: column-major n x ne per block at toff
+    int64_t *toff = nullptr;
+    double *F = nullptr, *H = nullptr, *dout = nullptr, *loss = nullptr;
+};
+
 struct DLeaf {
     int n = 0;
     int64_t *start = nullptr, *end = nullptr, *slot = nullptr;
@@ -82,6 +102,9 @@ struct Device {
     int64_t n_od = 0, n_id = 0;
     // near-field corrections (caller order, block CSR: 6 columns per element)
     DCorr corr, corrg;
+    DBJ bj;                      // block-Jacobi preconditioner (built on first use)
+    DLearn lt;                   // training data of the learned correction
+    double2 *gm_z = nullptr, *gm_t = nullptr;
     // GMRES work space (allocated on first solve)
     int gm_m = 0;
     double2 *gm_V = nullptr, *gm_w = nullptr, *gm_x = nullptr, *gm_r = nullptr, *gm_h = nullptr;
@@ -100,6 +123,24 @@ void device_upload(Plan &P);
 void device_free(Plan &P);
 void device_phase_average(Plan &P);
 void build_corrections_device(Plan &P, Device &D);
+void build_block_jacobi(Plan &P, Device &D);
+void apply_block_jacobi(Plan &P, const double2 *v, double2 *z, hipStream_t st, int mode);
+void learned_targets(Plan &P);
+
+struct LearnedNet;
+int learned_num_params();
+LearnedNet *learned_create(uint64_t seed);
+void learned_destroy(LearnedNet *N);
+void learned_set_params(LearnedNet *N, const double *th);
+void learned_get_params(LearnedNet *N, double *th);
+void learned_get_grad(LearnedNet *N, double *g);
+double learned_loss_grad(LearnedNet *N, Plan &P);
+double learned_train_step(LearnedNet *N, Plan &P, double lr);
+void learned_attach(LearnedNet *N, Plan &P);
+void learned_detach(Plan &P);
+double learned_loss_grad_raw(LearnedNet *N, int nb, const int64_t *poff, const int *bsize, const int *bne,
+                             const int64_t *boff, const int64_t *toff, int64_t n_rows, const double *F,
+                             const double2 *Binv, const double2 *T);
 void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st);
 void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t st);
 int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int restart, int precond, double2 *x,

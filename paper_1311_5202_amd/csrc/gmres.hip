@@ -119,6 +119,12 @@ __global__ void k_sub(const double2 *__restrict__ a, const double2 *__restrict__
     if (i < n) c[i] = make_double2(a[i].x - b[i].x, a[i].y - b[i].y);
 }
 
+__global__ void k_axpy1(const double2 *__restrict__ a, double2 *__restrict__ x, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = make_double2(x[i].x + a[i].x, x[i].y + a[i].y);
+}
+
 __global__ void k_zero(double2 *p, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -157,8 +163,15 @@ int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int r
     using cplx = std::complex<double>;
     Device &D = *P.dev;
     const int64_t n = P.N;
-    if (precond != 0) return -7;
+    if (precond < 0 || precond > 3) return -7;
+    if (precond && !D.bj.inv) build_block_jacobi(P, D);
+    if (precond == 2 && (!D.bj.O || D.bj.rank == 0)) return -7;
+    if (precond == 3) learned_targets(P);
     const int m = std::max(1, std::min(restart, maxit));
+    if (precond && !D.gm_z) {
+        HIP_CHECK(hipMalloc(&D.gm_z, sizeof(double2) * n));
+        HIP_CHECK(hipMalloc(&D.gm_t, sizeof(double2) * n));
+    }
     if (D.gm_m < m) {
         // (re)allocate the Krylov basis
         for (void *p : {(void *)D.gm_V, (void *)D.gm_w, (void *)D.gm_r, (void *)D.gm_h, (void *)D.gm_red_c})
@@ -197,7 +210,11 @@ int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int r
         bool done = false;
         for (; j < m && it < maxit; ++j) {
             double2 *vj = D.gm_V + (int64_t)j * n;
-            device_matvec(P, op, vj, D.gm_w, st);
+            if (precond) {
+                apply_block_jacobi(P, vj, D.gm_z, st, precond);
+                device_matvec(P, op, D.gm_z, D.gm_w, st);
+            } else
+                device_matvec(P, op, vj, D.gm_w, st);
             // CGS with one re-orthogonalisation
             std::vector<cplx> h(j + 2, cplx(0));
             for (int pass = 0; pass < 2; ++pass) {
@@ -255,7 +272,14 @@ int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int r
         std::vector<double2> yd(j);
         for (int q = 0; q < j; ++q) yd[q] = make_double2(y[q].real(), y[q].imag());
         HIP_CHECK(hipMemcpyAsync(D.gm_h, yd.data(), sizeof(double2) * j, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_add_combo, dim3(g), dim3(256), 0, st, D.gm_V, n, D.gm_h, j, x, n);
+        if (precond) {
+            // x += M (V y)
+            hipLaunchKernelGGL(k_zero, dim3(g), dim3(256), 0, st, D.gm_t, n);
+            hipLaunchKernelGGL(k_add_combo, dim3(g), dim3(256), 0, st, D.gm_V, n, D.gm_h, j, D.gm_t, n);
+            apply_block_jacobi(P, D.gm_t, D.gm_z, st, precond);
+            hipLaunchKernelGGL(k_axpy1, dim3(g), dim3(256), 0, st, D.gm_z, x, n);
+        } else
+            hipLaunchKernelGGL(k_add_combo, dim3(g), dim3(256), 0, st, D.gm_V, n, D.gm_h, j, x, n);
         // true residual
         device_matvec(P, op, x, D.gm_w, st);
         hipLaunchKernelGGL(k_sub, dim3(g), dim3(256), 0, st, b, D.gm_w, D.gm_r, n);

@@ -154,3 +154,87 @@ class Plan:
 
 def build(pts, nrm, w, k, eps, elements=None, **opts) -> Plan:
     return Plan(pts, nrm, w, k, eps, elements=elements, **opts)
+
+
+class Net:
+    """The learned low-rank correction of the block-Jacobi preconditioner
+    (fda_net_*): parameters live on the current GPU; training, evaluation and
+    the gradient run in the library's kernels."""
+
+    def __init__(self, seed: int = 0):
+        h = ctypes.c_void_p()
+        _abi.check(_abi.lib().fda_net_create(int(seed), ctypes.byref(h)))
+        self._h = h
+        self.n_params = int(_abi.lib().fda_net_num_params())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _abi.lib().fda_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self) -> np.ndarray:
+        th = np.empty(self.n_params)
+        _abi.check(_abi.lib().fda_net_get_params(self._h, th.ctypes.data))
+        return th
+
+    @params.setter
+    def params(self, th):
+        th = np.ascontiguousarray(th, dtype=np.float64).reshape(-1)
+        if th.shape[0] != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _abi.check(_abi.lib().fda_net_set_params(self._h, th.ctypes.data))
+
+    def loss_grad(self, plan: Plan):
+        loss = ctypes.c_double(0)
+        g = np.empty(self.n_params)
+        _abi.check(_abi.lib().fda_net_loss_grad(self._h, plan._h, ctypes.byref(loss), g.ctypes.data))
+        return loss.value, g
+
+    def train_step(self, plan: Plan, lr: float) -> float:
+        loss = ctypes.c_double(0)
+        _abi.check(_abi.lib().fda_net_train_step(self._h, plan._h, float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def attach(self, plan: Plan):
+        _abi.check(_abi.lib().fda_net_attach(self._h, plan._h))
+
+    @staticmethod
+    def detach(plan: Plan):
+        _abi.check(_abi.lib().fda_net_attach(None, plan._h))
+
+    def loss_grad_raw(self, pair_off, block_n, block_ne, inv_off, target_off, features, block_inv, targets):
+        """Loss and gradient on caller data (fda_net_loss_grad_raw): CUDA
+        tensors int64 pair_off, int32 block_n and block_ne, int64 inv_off and
+        target_off, float64 features (rows x 12), complex128 block_inv and
+        targets (column-major blocks at their offsets)."""
+        import torch
+
+        for t, dt in ((pair_off, torch.int64), (block_n, torch.int32), (block_ne, torch.int32),
+                      (inv_off, torch.int64), (target_off, torch.int64), (features, torch.float64),
+                      (block_inv, torch.complex128), (targets, torch.complex128)):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
+                raise ValueError(f"expected a contiguous {dt} CUDA tensor")
+        nb = pair_off.numel()
+        if any(t.numel() != nb for t in (block_n, block_ne, inv_off, target_off)) or nb == 0:
+            raise ValueError("inconsistent block layout")
+        if features.dim() != 2 or features.shape[1] != 12:
+            raise ValueError("features must be rows x 12")
+        n64 = block_n.to(torch.int64)
+        if int((inv_off + n64 * n64).max().item()) > block_inv.numel() or \
+                int((target_off + n64 * block_ne.to(torch.int64)).max().item()) > targets.numel():
+            raise ValueError("block arrays too short for the layout")
+        torch.cuda.synchronize()
+        loss = ctypes.c_double(0)
+        g = np.empty(self.n_params)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        _abi.check(_abi.lib().fda_net_loss_grad_raw(
+            self._h, nb, ptr(pair_off), ptr(block_n), ptr(block_ne), ptr(inv_off), ptr(target_off),
+            features.shape[0], ptr(features), ptr(block_inv), ptr(targets), ctypes.byref(loss), g.ctypes.data))
+        return loss.value, g

@@ -2,7 +2,8 @@
 
 This package holds geometry and random numbers only: closed surfaces given as
 curved quadratic triangles (six geometric nodes each), random complex
-densities and plane-wave directions.  It contains none of the method's
+densities and plane-wave directions, and random block data for the learned
+preconditioner's loss.  It contains none of the method's
 arithmetic (no quadrature rule, no kernel, no normal or weight computation);
 both the HIP path and the oracle derive those on their own.
 """
@@ -16,3 +17,4 @@ from .meshes import (  # noqa: F401
     random_directions,
     instance_batch,
 )
+from .blocks import learned_blocks  # noqa: F401
