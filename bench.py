@@ -5,6 +5,13 @@ One "step" is one full sound-hard Burton-Miller H mat-vec through the C ABI
 the near-field correction), on seeded random complex densities already
 resident in HBM.  Plan construction is not timed.
 
+Beside the headline rate the run reports the FP32 far/near-field mat-vec rate
+and its difference from FP64, and the GMRES time to a relative residual of
+1e-4 for a plane wave: plain FP64 against FP32 with the block-Jacobi plus
+learned coupling preconditioner (network trained here on small surfaces at the
+same points per wavelength; training and preconditioner set-up are reported
+separately).
+
 Prints one JSON line (rank 0) with the metric, the roofline of the dominant
 kernel and the oracle's CPU baseline on a bounded sample of rows.
 """
@@ -61,6 +68,69 @@ def cpu_baseline(pts, nrm, w, u, k, n_rows: int):
             "sample": f"dense FP64 H sum on {n_rows} of {len(w)} target rows ({dt:.1f} s), scaled to a full mat-vec"}
 
 
+def train_learned(fdb, synth, density: float, coupling: float, epochs: int, log):
+    """Train the coupling network on small star-shaped surfaces whose k gives
+    the same number of nodes per square wavelength as the benchmark body."""
+    import numpy as np
+
+    net = fdb.Net(11)
+    plans = []
+    t0 = time.perf_counter()
+    for s, n in enumerate((10, 12, 14, 16)):
+        el = synth.star_surface(n, seed=100 + s)
+        pts, nrm, w = fdb.nystrom_nodes(el)
+        k = 2 * np.pi * math.sqrt(len(w) / (density * w.sum()))
+        plans.append(fdb.build(pts, nrm, w, k, 1e-4, elements=el, corrections=1, coupling=coupling))
+    first = [net.loss_grad(p)[0] for p in plans]
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(epochs):
+        last = [net.train_step(p, 3e-3) for p in plans]
+    t_train = time.perf_counter() - t0
+    log(f"[bench] learned: loss {[round(v, 1) for v in first]} -> {[round(v, 1) for v in last]} "
+        f"({epochs} epochs, {t_train:.1f} s)")
+    for p in plans:
+        p.close()
+    return net, {"shapes": len(plans), "epochs": epochs, "setup_s": t_setup, "train_s": t_train,
+                 "loss_first": sum(first), "loss_last": sum(last)}
+
+
+def gmres_compare(fdb, synth, plan, tol: float, coupling: float, epochs: int, log):
+    """Time-to-tol of plain FP64 GMRES and of FP32 GMRES with the learned
+    preconditioner on the same plane-wave right-hand side."""
+    import numpy as np
+    import torch
+
+    rhs = plan.rhs_plane_wave([0.0, 0.0, 1.0])
+    out = {"tol": tol}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x64, i64 = plan.solve(rhs, tol, maxit=200, restart=200, precond=0, raise_on_fail=False)
+    torch.cuda.synchronize()
+    out["fp64_plain"] = {"iterations": i64["iterations"], "relres": i64["relres"], "status": i64["status"],
+                         "seconds": time.perf_counter() - t0}
+    log(f"[bench] FP64 plain GMRES: {out['fp64_plain']}")
+    w_sum = float(plan._w.sum())
+    density = plan.n * (2 * np.pi / plan.k) ** 2 / w_sum
+    net, out["training"] = train_learned(fdb, synth, density, coupling, epochs, log)
+    t0 = time.perf_counter()
+    net.attach(plan)
+    torch.cuda.synchronize()
+    out["preconditioner_setup_s"] = time.perf_counter() - t0
+    for name, pc in (("fp32_block_jacobi", 1), ("fp32_learned", 2)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = plan.solve(rhs, tol, maxit=200, restart=200, precond=pc, fp32=True, raise_on_fail=False)
+        torch.cuda.synchronize()
+        out[name] = {"iterations": info["iterations"], "relres": info["relres"], "status": info["status"],
+                     "seconds": time.perf_counter() - t0,
+                     "rel_diff_vs_fp64": (torch.linalg.norm(x - x64) / torch.linalg.norm(x64)).item()}
+        log(f"[bench] {name} GMRES: {out[name]}")
+    net.close()
+    out["speedup_fp32_learned_vs_fp64_plain"] = out["fp64_plain"]["seconds"] / out["fp32_learned"]["seconds"]
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +139,10 @@ def main() -> int:
     ap.add_argument("--workload", default=os.environ.get("FDBEM_WORKLOAD", "c5"), choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0)
+    ap.add_argument("--no-solve", action="store_true", help="skip the GMRES time-to-tolerance comparison")
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--coupling", type=float, default=-1.0,
+                    help="Burton-Miller alpha = i*coupling/k; 1 is the value the paper states, -1 its conjugate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -84,7 +158,8 @@ def main() -> int:
     pts, nrm, w = fdb.nystrom_nodes(el)
     N = len(w)
     t0 = time.perf_counter()
-    plan = fdb.build(pts, nrm, w, k, eps, elements=el, corrections=1, verbose=1)
+    plan = fdb.build(pts, nrm, w, k, eps, elements=el, corrections=1, verbose=1, precision="both",
+                     coupling=args.coupling)
     t_build = time.perf_counter() - t0
     st = plan.stats()
     print(f"[bench] workload={args.workload} N={N} k={k} p2p_pairs={st['p2p_pairs']} build {t_build:.1f} s m2l_tile={st.get('m2l_tile')} tiles(t,ch,p,seg)={st.get('m2l_tiles')} lds={st.get('m2l_lds_bytes')}/{st.get('max_lds_per_block')}", file=sys.stderr, flush=True)
@@ -107,6 +182,18 @@ def main() -> int:
     phases = plan.phase_times()
     plan.set_timing(False)
     torch.cuda.synchronize()
+    # FP32 far and near field on the same densities
+    out32 = torch.empty_like(u)
+    plan.matvec(u, op, out=out32, fp32=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.matvec(u, op, out=out32, fp32=True)
+    torch.cuda.synchronize()
+    dt32 = time.perf_counter() - t0
+    fp32 = {"matvec_per_s": args.steps / dt32,
+            "rel_l2_vs_fp64": (torch.linalg.norm(out32 - out) / torch.linalg.norm(out)).item()}
+    print(f"[bench] FP32 mat-vec {fp32}", file=sys.stderr, flush=True)
     ms = 1e3 * dt / args.steps
     flops, byts = m2l_work(st)
     m2l_ms = phases["m2l"]
@@ -136,11 +223,16 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "N": N, "k": k, "eps": eps, "operator": op, "parallelism": "single GPU"},
+        "config": {"workload": desc, "N": N, "k": k, "eps": eps, "operator": op,
+                   "alpha": f"{args.coupling:g}i/k", "parallelism": "single GPU"},
         "phase_ms": phases,
         "build_s": t_build,
         "roofline": roof,
+        "fp32": fp32,
     }
+    if not args.no_solve and op == "BM_H":
+        log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+        res["gmres"] = gmres_compare(fdb, synth, plan, 1e-4, args.coupling, args.epochs, log)
     if not args.no_cpu_baseline:
         n_rows = args.cpu_rows or max(64, min(N, int(2.5e9 / N)))
         res["cpu_baseline"] = cpu_baseline(pts, nrm, w, u_host, k, n_rows)

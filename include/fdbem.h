@@ -90,6 +90,9 @@ typedef struct {
     int m2l_tile;       /* M2L target tile size; 0 -> largest that fits LDS, < 0 -> per-target kernel */
     double p2p_threshold; /* a far pair whose point counts multiply to at most this is summed
                              directly instead of translated; 0 -> 400, < 0 -> never */
+    double coupling;    /* Burton-Miller coupling alpha = i * coupling / k (section 2.1,
+                           eq. eq_bm); 0 -> 1, the value the paper uses.  -1 gives the
+                           conjugate coupling (see bm_solve). */
 } fda_opts;
 
 typedef struct fda_plan fda_plan;
@@ -108,12 +111,13 @@ int bem_nystrom_nodes(int64_t n_elem, const double *elem, double *pts, double *n
  * over the nodes j of the elements in the local region D_i of x_i (elements
  * whose distance to x_i is at most twice their longest side).  op is
  * FDA_OP_BM_H (K = dG/dn_y + alpha d2G/dn_x dn_y) or FDA_OP_BM_G
- * (K = G + alpha dG/dn_x).  Call with row_ptr = col = val = NULL to get
+ * (K = G + alpha dG/dn_x), alpha = i coupling / k (coupling 0 -> 1).  Call with row_ptr = col = val = NULL to get
  * *nnz_out; then with row_ptr (n_nodes+1), col (nnz) and val (2*nnz doubles,
  * interleaved complex) to fill them.  Nodes must be those of
  * bem_nystrom_nodes for the same elements. */
 int bem_near_correction(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,
-                        double k, int op, int64_t *nnz_out, int64_t *row_ptr, int64_t *col, double *val);
+                        double k, int op, double coupling, int64_t *nnz_out, int64_t *row_ptr, int64_t *col,
+                        double *val);
 
 /* Build a plan on the current HIP device: octree and lists (section 3.1.1),
  * point templates and pseudo-inverses (section 3.1.2, eqs. eq_svdr/eq_invr),

@@ -37,7 +37,8 @@ class FdaOpts(ctypes.Structure):
                 ("leaf_rule", ctypes.c_int), ("c_d", ctypes.c_double), ("far_field", ctypes.c_int),
                 ("lf_grid", ctypes.c_int), ("precision", ctypes.c_int), ("corrections", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("wedge_factor", ctypes.c_int), ("m2l_tile", ctypes.c_int),
-                ("p2p_threshold", ctypes.c_double)]
+                ("p2p_threshold", ctypes.c_double),
+                ("coupling", ctypes.c_double)]
 
 
 class FdaError(RuntimeError):
@@ -60,7 +61,7 @@ def lib() -> ctypes.CDLL:
     vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     L.fda_default_opts.argtypes = [ctypes.POINTER(FdaOpts)]
     L.bem_nystrom_nodes.argtypes = [i64, vp, vp, vp, vp]
-    L.bem_near_correction.argtypes = [i64, vp, vp, vp, vp, dbl, ci, ctypes.POINTER(i64), vp, vp, vp]
+    L.bem_near_correction.argtypes = [i64, vp, vp, vp, vp, dbl, ci, dbl, ctypes.POINTER(i64), vp, vp, vp]
     L.fda_build.argtypes = [ctypes.POINTER(FdaGeometry), dbl, dbl, ctypes.POINTER(FdaOpts), ctypes.POINTER(vp)]
     L.fda_matvec.argtypes = [vp, ci, vp, vp, vp]
     L.bm_solve.argtypes = [vp, ci, vp, dbl, ci, ci, ci, vp, ctypes.POINTER(ci), ctypes.POINTER(dbl), vp, vp]

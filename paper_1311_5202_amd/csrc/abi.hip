@@ -75,6 +75,7 @@ int fda_default_opts(fda_opts *o)
     o->wedge_factor = d.wedge_factor;
     o->m2l_tile = 0;
     o->p2p_threshold = 0;
+    o->coupling = 1.0;
     return FDA_OK;
 }
 
@@ -88,15 +89,17 @@ int bem_nystrom_nodes(int64_t n_elem, const double *elem, double *pts, double *n
 }
 
 int bem_near_correction(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,
-                        double k, int op, int64_t *nnz_out, int64_t *row_ptr, int64_t *col, double *val)
+                        double k, int op, double coupling, int64_t *nnz_out, int64_t *row_ptr, int64_t *col,
+                        double *val)
 {
     return guarded([&] {
         if (n_elem <= 0 || !elem || !pts || !nrm || !w || !nnz_out) throw std::invalid_argument("null argument");
         if (!(k > 0) || !std::isfinite(k)) throw std::invalid_argument("wavenumber must be positive");
         if (op != FDA_OP_BM_H && op != FDA_OP_BM_G) throw std::invalid_argument("op must be FDA_OP_BM_H or FDA_OP_BM_G");
+        if (!std::isfinite(coupling)) throw std::invalid_argument("non-finite coupling");
         std::vector<int64_t> rp, cl;
         std::vector<cplx> vl;
-        correction_table_host(n_elem, elem, pts, nrm, w, k, op, rp, cl, vl);
+        correction_table_host(n_elem, elem, pts, nrm, w, k, op, coupling != 0 ? coupling : 1.0, rp, cl, vl);
         *nnz_out = (int64_t)cl.size();
         if (row_ptr && col && val) {
             std::memcpy(row_ptr, rp.data(), sizeof(int64_t) * rp.size());
@@ -127,6 +130,8 @@ int fda_build(const fda_geometry *g, double k, double eps, const fda_opts *o, fd
             opt.wedge_factor = o->wedge_factor > 0 ? o->wedge_factor : opt.wedge_factor;
             opt.m2l_tile = o->m2l_tile;
             if (o->p2p_threshold != 0) opt.p2p_threshold = o->p2p_threshold;
+            if (!std::isfinite(o->coupling)) throw std::invalid_argument("non-finite coupling");
+            opt.coupling = o->coupling != 0 ? o->coupling : 1.0;
         }
         if (opt.precision < FDA_PREC_FP64 || opt.precision > FDA_PREC_BOTH) throw std::invalid_argument("unknown precision");
         if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");

@@ -207,13 +207,14 @@ template <int OPK, typename R>
 __global__ __launch_bounds__(256) void k_p2p(int n_leaf, const int64_t *__restrict__ ts, const int64_t *__restrict__ te,
                                              const int *__restrict__ ptr, const int64_t *__restrict__ ss,
                                              const int64_t *__restrict__ se, const PN *__restrict__ pn,
-                                             const double2 *__restrict__ dens, double2 *__restrict__ res, double k)
+                                             const double2 *__restrict__ dens, double2 *__restrict__ res, double k,
+                                             double alpha_im)
 {
     using C = typename Cx<R>::T;
     const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (leaf >= n_leaf) return;
     const int lane = threadIdx.x & 63;
-    const R kr = (R)k, ik = (R)(1.0 / k);
+    const R kr = (R)k, ik = (R)alpha_im;
     const int64_t t0 = ts[leaf], t1 = te[leaf];
     const int e0 = ptr[leaf], e1 = ptr[leaf + 1];
     for (int64_t ib = t0; ib < t1; ib += 64) {
@@ -627,16 +628,16 @@ __global__ void k_corr(const int64_t *__restrict__ rp, const int32_t *__restrict
 
 __global__ void k_plane_wave(const double *__restrict__ X, const double *__restrict__ Y, const double *__restrict__ Z,
                              const double *__restrict__ NX, const double *__restrict__ NY, const double *__restrict__ NZ,
-                             const int64_t *__restrict__ perm, double k, double d0, double d1, double d2,
-                             double2 *__restrict__ rhs, int64_t n)
+                             const int64_t *__restrict__ perm, double k, double coupling, double d0, double d1,
+                             double d2, double2 *__restrict__ rhs, int64_t n)
 {
-    // b = u_inc + alpha du_inc/dn_x, u_inc = exp(ik x.d), du_inc/dn = ik (d.n) u_inc, alpha = i/k
-    // => b = u_inc (1 + (i/k)(ik)(d.n)) = u_inc (1 - d.n)
+    // b = u_inc + alpha du_inc/dn_x, u_inc = exp(ik x.d), du_inc/dn = ik (d.n) u_inc, alpha = i c/k
+    // => b = u_inc (1 + (i c/k)(ik)(d.n)) = u_inc (1 - c d.n)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double sn, cs;
     sincos(k * (X[i] * d0 + Y[i] * d1 + Z[i] * d2), &sn, &cs);
-    const double f = 1.0 - (NX[i] * d0 + NY[i] * d1 + NZ[i] * d2);
+    const double f = 1.0 - coupling * (NX[i] * d0 + NY[i] * d1 + NZ[i] * d2);
     rhs[perm[i]] = make_double2(cs * f, sn * f);
 }
 
@@ -940,9 +941,10 @@ void device_free(Plan &P)
     P.dev = nullptr;
 }
 
-static OpC op_coef(int op, double k)
+// coefficients of K = (c0 + c1 d/dn_y)(d0 + d1 d/dn_x) G with alpha = i / ka
+static OpC op_coef(int op, double ka)
 {
-    const double2 z = make_double2(0, 0), one = make_double2(1, 0), al = make_double2(0, 1.0 / k);
+    const double2 z = make_double2(0, 0), one = make_double2(1, 0), al = make_double2(0, 1.0 / ka);
     OpC c;
     switch (op) {
     case 0:  // RAW_H
@@ -978,15 +980,16 @@ static void launch_p2p(Plan &P, Device &D, int op, hipStream_t st)
 {
     const int opk = (op == 0 || op == 3) ? OPK_H : (op == 1 || op == 4) ? OPK_G : OPK_T1;
     const dim3 g((D.n_leaf + 3) / 4), b(256);
+    const double ai = 1.0 / P.opt.alpha_k(P.k);
     if (opk == OPK_H)
         hipLaunchKernelGGL((k_p2p<OPK_H, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
-                           (const PN *)D.pn, D.dens, D.res, P.k);
+                           (const PN *)D.pn, D.dens, D.res, P.k, ai);
     else if (opk == OPK_G)
         hipLaunchKernelGGL((k_p2p<OPK_G, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
-                           (const PN *)D.pn, D.dens, D.res, P.k);
+                           (const PN *)D.pn, D.dens, D.res, P.k, ai);
     else
         hipLaunchKernelGGL((k_p2p<OPK_T1, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss,
-                           D.p2p_se, (const PN *)D.pn, D.dens, D.res, P.k);
+                           D.p2p_se, (const PN *)D.pn, D.dens, D.res, P.k, ai);
 }
 
 template <int TAG, bool TRANS, typename R>
@@ -1034,7 +1037,7 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
     // near field on plans built with both precisions
     const bool f32 = D.prec == 1 || (D.prec == 2 && (op & 0x100));
     op &= 0xff;
-    const OpC c = op_coef(op, P.k);
+    const OpC c = op_coef(op, P.opt.alpha_k(P.k));
     const bool tm = D.timing != 0;
     hipEvent_t *ev = tm ? &D.ev[(size_t)(D.ring_pos % Device::kRing) * 10] : nullptr;
     if (tm) HIP_CHECK(hipEventRecord(ev[0], st));
@@ -1133,7 +1136,7 @@ void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t
 {
     Device &D = *P.dev;
     hipLaunchKernelGGL(k_plane_wave, dim3(nblk(P.N, 256)), dim3(256), 0, st, D.x, D.y, D.z, D.nx, D.ny, D.nz, D.perm,
-                       P.k, d[0], d[1], d[2], rhs, P.N);
+                       P.k, P.opt.coupling, d[0], d[1], d[2], rhs, P.N);
     HIP_CHECK(hipGetLastError());
 }
 

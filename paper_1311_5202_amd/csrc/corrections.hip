@@ -435,9 +435,10 @@ Tables make_tables()
     return T;
 }
 
-Coef op_coef(int op, double k)
+// coefficients of K = (c0 + c1 d/dn_y)(d0 + d1 d/dn_x) G with alpha = i / ka
+Coef op_coef(int op, double ka)
 {
-    const Z al = {0.0, 1.0 / k}, one = {1.0, 0.0}, zero = {0.0, 0.0};
+    const Z al = {0.0, 1.0 / ka}, one = {1.0, 0.0}, zero = {0.0, 0.0};
     return op == 3 ? Coef{zero, one, one, al} : Coef{one, zero, one, al};
 }
 
@@ -553,13 +554,13 @@ __global__ __launch_bounds__(128) void k_corr_weights(int64_t n, const int64_t *
 
 // Host table (expanded CSR) for bem_near_correction.
 void correction_table_host(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,
-                           double k, int op, std::vector<int64_t> &rp, std::vector<int64_t> &col,
+                           double k, int op, double coupling, std::vector<int64_t> &rp, std::vector<int64_t> &col,
                            std::vector<cplx> &val)
 {
     using namespace nq;
     const int64_t N = 6 * n_elem;
     const Tables T = make_tables();
-    const Coef c = op_coef(op, k);
+    const Coef c = op_coef(op, k / coupling);
     Candidates C = candidates(n_elem, elem, pts);
     std::vector<unsigned char> keep(C.elem.size());
     std::vector<Z> v6(6 * C.elem.size());
@@ -656,7 +657,7 @@ void build_corrections_device(Plan &P, Device &D)
             HIP_CHECK(hipMalloc(&dval, sizeof(double2) * 6 * (size_t)std::max<int64_t>(nk, 1)));
             D.allocs.push_back(dval);
             D.bytes += sizeof(double2) * 6 * (size_t)nk;
-            const Coef c = op_coef(op, P.k);
+            const Coef c = op_coef(op, P.opt.alpha_k(P.k));
             // launch in slices so no single dispatch runs for long
             const int64_t slice = 1 << 20;
             for (int64_t b = 0; b < nk; b += slice) {

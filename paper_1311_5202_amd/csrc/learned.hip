@@ -61,7 +61,8 @@ __device__ __forceinline__ double2 zdiv(double2 a, double2 b)
     return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
-__device__ inline double2 h_kernel(const double *x, const double *nx, const double *y, const double *ny, double k)
+__device__ inline double2 h_kernel(const double *x, const double *nx, const double *y, const double *ny, double k,
+                                   double ik)
 {
     const double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
     const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2), ir = 1.0 / r;
@@ -76,7 +77,6 @@ __device__ inline double2 h_kernel(const double *x, const double *nx, const doub
     const double2 q = make_double2(k * k - 3.0 * ir * ir, 3.0 * k * ir);
     const double p = dnx * dny, f = nn * ir;
     const double2 B = make_double2(q.x * p + a.x * f, q.y * p + a.y * f);
-    const double ik = 1.0 / k;
     return zmul(G, make_double2(a.x * dny - B.y * ik, a.y * dny + B.x * ik));
 }
 
@@ -85,7 +85,7 @@ __device__ inline double2 h_kernel(const double *x, const double *nx, const doub
 __global__ void k_ext_assemble(const int *__restrict__ ne_, const int64_t *__restrict__ ext,
                                const double *__restrict__ X, const double *__restrict__ NX, const double *__restrict__ W,
                                const int64_t *__restrict__ crp, const int32_t *__restrict__ cblk,
-                               const double2 *__restrict__ cval, double k, double2 *__restrict__ A)
+                               const double2 *__restrict__ cval, double k, double alpha_im, double2 *__restrict__ A)
 {
     const int b = blockIdx.y;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -96,7 +96,7 @@ __global__ void k_ext_assemble(const int *__restrict__ ne_, const int64_t *__res
     if (i < ne && j < ne) {
         const int64_t gi = ext[(size_t)b * EXT + i], gj = ext[(size_t)b * EXT + j];
         if (i != j) {
-            const double2 K = h_kernel(X + 3 * gi, NX + 3 * gi, X + 3 * gj, NX + 3 * gj, k);
+            const double2 K = h_kernel(X + 3 * gi, NX + 3 * gi, X + 3 * gj, NX + 3 * gj, k, alpha_im);
             v = zadd(v, make_double2(K.x * W[gj], K.y * W[gj]));
         }
         const int32_t ej = (int32_t)(gj / 6);
@@ -573,7 +573,8 @@ static void ensure_targets(Plan &P, Device &D)
     for (int b0 = 0; b0 < nb; b0 += batch) {
         const int m = std::min(batch, nb - b0);
         hipLaunchKernelGGL(lp::k_ext_assemble, dim3(lp::EXT * lp::EXT / 256, m), dim3(256), 0, 0, D.bj.ne + b0,
-                           D.bj.ext + (size_t)b0 * lp::EXT, g.X, g.NX, g.W, D.corr.rp, D.corr.blk, D.corr.val, P.k, dA);
+                           D.bj.ext + (size_t)b0 * lp::EXT, g.X, g.NX, g.W, D.corr.rp, D.corr.blk, D.corr.val, P.k,
+                           1.0 / P.opt.alpha_k(P.k), dA);
         hipLaunchKernelGGL(lp::k_ext_invert, dim3(m), dim3(256), 0, 0, dA, dfail);
         hipLaunchKernelGGL(lp::k_ras_extract, dim3(m), dim3(256), 0, 0, D.bj.size + b0, D.bj.ne + b0, D.lt.toff + b0,
                            dA, D.lt.T);

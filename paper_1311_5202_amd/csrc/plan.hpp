@@ -29,6 +29,9 @@ struct Options {
     int precision = 0;       // 0 FP64, 1 FP32 far field
     int corrections = 1;     // build local corrections when elements are supplied
     int verbose = 0;
+    double coupling = 1.0;   // Burton-Miller alpha = i coupling / k
+    // k of the coupling: alpha = i / alpha_k()
+    double alpha_k(double k) const { return k / coupling; }
 };
 
 struct Cube {
@@ -183,7 +186,7 @@ void build_m2l_tiles(Plan &P, int tile, int chunk);
 void build_m2l_chunks(Plan &P, int chunk);
 M2LChunks build_chunks(const GemvList &G, int chunk);
 void correction_table_host(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,
-                           double k, int op, std::vector<int64_t> &rp, std::vector<int64_t> &col,
+                           double k, int op, double coupling, std::vector<int64_t> &rp, std::vector<int64_t> &col,
                            std::vector<cplx> &val);
 void nystrom_nodes(int64_t n_elem, const double *elem, double *pts, double *nrm, double *w);
 void gauss6(double xi[6][2], double wq[6]);

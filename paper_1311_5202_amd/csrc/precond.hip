@@ -40,8 +40,9 @@ __device__ __forceinline__ double2 zdiv(double2 a, double2 b)
     return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
-// dG/dn_y + alpha d2G/dn_x dn_y, alpha = i/k
-__device__ inline double2 h_kernel(const double *x, const double *nx, const double *y, const double *ny, double k)
+// dG/dn_y + alpha d2G/dn_x dn_y, alpha = i ik
+__device__ inline double2 h_kernel(const double *x, const double *nx, const double *y, const double *ny, double k,
+                                   double ik)
 {
     const double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
     const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2), ir = 1.0 / r;
@@ -56,7 +57,6 @@ __device__ inline double2 h_kernel(const double *x, const double *nx, const doub
     const double2 q = make_double2(k * k - 3.0 * ir * ir, 3.0 * k * ir);
     const double p = dnx * dny, f = nn * ir;
     const double2 B = make_double2(q.x * p + a.x * f, q.y * p + a.y * f);
-    const double ik = 1.0 / k;
     return zmul(G, make_double2(a.x * dny - B.y * ik, a.y * dny + B.x * ik));
 }
 
@@ -68,7 +68,8 @@ __global__ __launch_bounds__(64) void k_bj_build(const int64_t *__restrict__ bst
                                                  const double *__restrict__ X, const double *__restrict__ NX,
                                                  const double *__restrict__ W, const int64_t *__restrict__ crp,
                                                  const int32_t *__restrict__ cblk, const double2 *__restrict__ cval,
-                                                 double k, double2 *__restrict__ inv, int *__restrict__ fail)
+                                                 double k, double alpha_im, double2 *__restrict__ inv,
+                                                 int *__restrict__ fail)
 {
     __shared__ double2 A[BJ_MAX * BJ_MAX];
     __shared__ int64_t ci[BJ_MAX];
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(64) void k_bj_build(const int64_t *__restrict__ bst
         const int64_t gi = ci[i], gj = ci[j];
         double2 v = make_double2(i == j ? 0.5 : 0.0, 0.0);
         if (i != j) {
-            const double2 K = h_kernel(X + 3 * gi, NX + 3 * gi, X + 3 * gj, NX + 3 * gj, k);
+            const double2 K = h_kernel(X + 3 * gi, NX + 3 * gi, X + 3 * gj, NX + 3 * gj, k, alpha_im);
             v = zadd(v, make_double2(K.x * W[gj], K.y * W[gj]));
         }
         // correction entry (gi, gj): element gj / 6 in the row's blocks
@@ -280,7 +281,7 @@ void build_block_jacobi(Plan &P, Device &D)
     HIP_CHECK(hipMemcpy(dW, W.data(), 8 * W.size(), hipMemcpyHostToDevice));
     HIP_CHECK(hipMemset(dfail, 0, sizeof(int)));
     hipLaunchKernelGGL(k_bj_build, dim3(nb), dim3(64), 0, 0, D.bj.start, D.bj.size, D.bj.off, D.perm, dX, dNX, dW,
-                       D.corr.rp, D.corr.blk, D.corr.val, P.k, D.bj.inv, dfail);
+                       D.corr.rp, D.corr.blk, D.corr.val, P.k, 1.0 / P.opt.alpha_k(P.k), D.bj.inv, dfail);
     HIP_CHECK(hipGetLastError());
     int fail = 0;
     HIP_CHECK(hipMemcpy(&fail, dfail, sizeof(int), hipMemcpyDeviceToHost));

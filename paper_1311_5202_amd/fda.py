@@ -24,9 +24,9 @@ def nystrom_nodes(elements: np.ndarray):
     return pts, nrm, w
 
 
-def near_correction(elements, pts, nrm, w, k: float, op: str = "BM_H"):
+def near_correction(elements, pts, nrm, w, k: float, op: str = "BM_H", coupling: float = 1.0):
     """Host CSR table (row_ptr, col, val) of the locally corrected near field
-    (bem_near_correction), caller node order."""
+    (bem_near_correction), caller node order; alpha = i coupling / k."""
     import scipy.sparse as sp
 
     el = np.ascontiguousarray(elements, dtype=np.float64).reshape(-1, 6, 3)
@@ -35,7 +35,8 @@ def near_correction(elements, pts, nrm, w, k: float, op: str = "BM_H"):
     w = np.ascontiguousarray(w, dtype=np.float64)
     L = _abi.lib()
     nnz = ctypes.c_int64(0)
-    args = (el.shape[0], el.ctypes.data, pts.ctypes.data, nrm.ctypes.data, w.ctypes.data, float(k), _abi.OPS[op])
+    args = (el.shape[0], el.ctypes.data, pts.ctypes.data, nrm.ctypes.data, w.ctypes.data, float(k), _abi.OPS[op],
+            float(coupling))
     _abi.check(L.bem_near_correction(*args, ctypes.byref(nnz), None, None, None))
     n = 6 * el.shape[0]
     rp = np.empty(n + 1, dtype=np.int64)

@@ -11,18 +11,22 @@ import synth
 from oracle import near
 
 
-@pytest.mark.parametrize("op,oop,free,tol", [("BM_H", "H", 0.5, 1e-7), ("BM_G", "G", 0.0, 2e-6)])
-def test_correction_table_matches_oracle(op, oop, free, tol):
+@pytest.mark.parametrize("op,oop,free,tol,coupling", [("BM_H", "H", 0.5, 1e-7, 1.0), ("BM_G", "G", 0.0, 2e-6, 1.0),
+                                                      ("BM_H", "H", 0.5, 1e-7, -1.0)])
+def test_correction_table_matches_oracle(op, oop, free, tol, coupling):
     el = synth.octa_sphere(6)
     pts, nrm, w = fdb.nystrom_nodes(el)
     k = 4.0
-    C = fdb.near_correction(el, pts, nrm, w, k, op)
+    C = fdb.near_correction(el, pts, nrm, w, k, op, coupling=coupling)
     n = len(w)
     assert C.shape == (n, n)
     u = synth.random_densities(n, 5)
     rows = np.arange(0, n, 11)
-    prod = free * u[rows] + oracle.dense_rows(pts, nrm, w, u, k, oop, rows=rows) + (C @ u)[rows]
-    ref = near.corrected_rows(el, u, k, oop, rows=rows)
+    # alpha = i coupling / k in both products (eq. eq_bm)
+    c0, c1, d0, _ = oracle.op_coefficients(oop, k)
+    coefs = (c0, c1, d0, 1j * coupling / k)
+    prod = free * u[rows] + oracle.dense_rows(pts, nrm, w, u, k, oop, rows=rows, coefs=coefs) + (C @ u)[rows]
+    ref = near.corrected_rows(el, u, k, oop, rows=rows, coefs=coefs)
     assert oracle.rel_l2(prod, ref) < tol
 
 

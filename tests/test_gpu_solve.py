@@ -123,3 +123,39 @@ def test_fp32_solve_matches_fp64(torch):
     print("iterations fp64", i64["iterations"], "fp32", i32["iterations"], "difference", d)
     assert i32["status"] == 0 and d < 5e-4
     plan.close()
+
+
+def test_conjugate_coupling_operator_and_solve(torch):
+    """alpha = -i/k (coupling = -1): the operator matches the oracle with that
+    alpha, the plane-wave solve reaches the same Mie surface field (any
+    Im alpha != 0 gives the unique exterior solution), with fewer GMRES
+    iterations than the paper's alpha = i/k at this k."""
+    import paper_1311_5202_amd as fdb
+
+    k = 12.0
+    d = np.array([0.0, 0.0, 1.0])
+    el = synth.octa_sphere(12)
+    pts, nrm, w = fdb.nystrom_nodes(el)
+    print(f"[plan] N={len(w)} k={k} coupling=-1", flush=True)
+    plan = fdb.build(pts, nrm, w, k, 1e-4, elements=el, corrections=1, coupling=-1.0)
+    u = synth.random_densities(len(w), 4)
+    rows = np.arange(0, len(w), 37)
+    got = plan.matvec(torch.from_numpy(u).cuda(), "BM_H").cpu().numpy()
+    ref = near.corrected_rows(el, u, k, "H", rows=rows, coefs=(0.0, 1.0, 1.0, -1j / k))
+    err = oracle.rel_l2(got[rows], ref)
+    print("operator error", err)
+    assert err <= 1e-4
+    b = plan.rhs_plane_wave(d)
+    uinc = np.exp(1j * k * pts @ d)
+    assert np.max(np.abs(b.cpu().numpy() - uinc * (1 + nrm @ d))) < 1e-13
+    x, info = plan.solve(b, 1e-6, maxit=300, restart=300)
+    mie_err = oracle.rel_l2(x.cpu().numpy(), _mie_total(pts, k, d))
+    plan_p = fdb.build(pts, nrm, w, k, 1e-4, elements=el, corrections=1)
+    xp, info_p = plan_p.solve(plan_p.rhs_plane_wave(d), 1e-6, maxit=300, restart=300)
+    mie_err_p = oracle.rel_l2(xp.cpu().numpy(), _mie_total(pts, k, d))
+    print(f"iterations conjugate {info['iterations']} paper {info_p['iterations']}; "
+          f"Mie error {mie_err:.2e} / {mie_err_p:.2e}", flush=True)
+    assert mie_err <= 2e-2 and abs(mie_err - mie_err_p) <= 0.5 * mie_err_p
+    assert info["iterations"] < info_p["iterations"]
+    plan.close()
+    plan_p.close()
