@@ -141,6 +141,8 @@ def main() -> int:
     ap.add_argument("--cpu-rows", type=int, default=0)
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES time-to-tolerance comparison")
     ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--coupling", type=float, default=-1.0,
                     help="Burton-Miller alpha = i*coupling/k; 1 is the value the paper states, -1 its conjugate")
     args = ap.parse_args()
@@ -153,6 +155,13 @@ def main() -> int:
     import paper_1311_5202_amd as fdb
     import synth
 
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n_split, k, eps, desc = WORKLOADS[args.workload]
     el = synth.octa_sphere(n_split)
     pts, nrm, w = fdb.nystrom_nodes(el)
