@@ -87,7 +87,10 @@ typedef struct {
     int corrections;    /* bit 0: corrected H table, bit 1: corrected G table (needs elements) */
     int verbose;
     int wedge_factor;   /* directional wedges: cells per cube-face edge = wedge_factor * w / lambda; 0 -> 2 */
-    int m2l_tile;       /* M2L target tile size; 0 -> largest that fits LDS, < 0 -> per-target kernel */
+    int m2l_tile;       /* translation schedule: 0 -> operator chunks whose per-pair results
+                           are summed per output in a fixed order (deterministic, default),
+                           1 -> operator chunks with atomic adds, > 1 -> workgroup M2L tiles
+                           of that size, < 0 -> per-target GEMV */
     double p2p_threshold; /* a far pair whose point counts multiply to at most this is summed
                              directly instead of translated; 0 -> 400, < 0 -> never */
     double coupling;    /* Burton-Miller coupling alpha = i * coupling / k (section 2.1,

@@ -538,7 +538,7 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int TAG, bool TRANS, typename R>
+template <int TAG, bool TRANS, typename R, bool PART>
 __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks(int n_chunks, int s, int cols, int rmax,
                                                             const int64_t *__restrict__ ch_mat,
                                                             const int *__restrict__ ch_rank,
@@ -547,7 +547,9 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks(int n_chunks, int s,
                                                             const int64_t *__restrict__ pr_src,
                                                             const typename Cx<R>::T *__restrict__ mat,
                                                             const typename Cx<R>::T *__restrict__ od,
-                                                            typename Cx<R>::T *id)
+                                                            typename Cx<R>::T *id,
+                                                            const int64_t *__restrict__ pr_pos,
+                                                            typename Cx<R>::T *__restrict__ part)
 {
     using C = typename Cx<R>::T;
     extern __shared__ unsigned char shraw[];
@@ -601,15 +603,39 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks(int n_chunks, int s,
 #pragma unroll
         for (int p = 0; p < M2LC_CH; ++p)
             if (p < n) {
-                R *o = (R *)(id + pr_tgt[p0 + p] + row);
-                atomicAdd(o, acc[p].x);
-                atomicAdd(o + 1, acc[p].y);
+                if (PART) {
+                    part[pr_pos[p0 + p] * s + row] = acc[p];
+                } else {
+                    R *o = (R *)(id + pr_tgt[p0 + p] + row);
+                    atomicAdd(o, acc[p].x);
+                    atomicAdd(o + 1, acc[p].y);
+                }
             }
     }
 }
 
 // Near-field correction, caller order: out_i += sum over the node's element
 // blocks of sum_g val_bg in_{6 e_b + g}.
+// Sum of the per-pair results of each output slot (entries contiguous in
+// target-major order), one wavefront per output, lanes over rows.
+template <typename R>
+__global__ __launch_bounds__(256) void k_seg_sum(int n_out, int s, const int64_t *__restrict__ red_out,
+                                                 const int64_t *__restrict__ red_ptr,
+                                                 const typename Cx<R>::T *__restrict__ part,
+                                                 typename Cx<R>::T *out)
+{
+    using C = typename Cx<R>::T;
+    const int o = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (o >= n_out) return;
+    const int64_t e0 = red_ptr[o], e1 = red_ptr[o + 1];
+    C *dst = out + red_out[o];
+    for (int row = lane; row < s; row += 64) {
+        C a = Cx<R>::mk(0, 0);
+        for (int64_t e = e0; e < e1; ++e) a = cadd(a, part[e * s + row]);
+        dst[row] = cadd(dst[row], a);
+    }
+}
+
 __global__ void k_corr(const int64_t *__restrict__ rp, const int32_t *__restrict__ blk,
                        const double2 *__restrict__ val, const double2 *__restrict__ in, double2 *__restrict__ out,
                        int64_t n)
@@ -715,6 +741,13 @@ static DChunks upload_chunks(Device &D, const M2LChunks &C)
     d.ch_pptr = dupload(D, C.ch_pptr);
     d.pr_tgt = dupload(D, C.pr_tgt);
     d.pr_src = dupload(D, C.pr_src);
+    if (!C.red_out.empty()) {
+        d.n_out = (int)C.red_out.size();
+        d.n_entries = (int64_t)C.pr_pos.size();
+        d.pr_pos = dupload(D, C.pr_pos);
+        d.red_out = dupload(D, C.red_out);
+        d.red_ptr = dupload(D, C.red_ptr);
+    }
     return d;
 }
 
@@ -805,9 +838,45 @@ void device_upload(Plan &P)
         }
         int maxsh = 65536;
         (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, D.device);
-        // M2L mode: 0 operator chunks with atomics (default), 1 per-target GEMV,
-        // 2 deterministic target tiles
-        D.m2l_mode = P.opt.m2l_tile < 0 ? 1 : P.opt.m2l_tile > 0 ? 2 : 0;
+        // M2L mode: 3 operator chunks with per-pair results summed per output
+        // (default, deterministic), 0 operator chunks with atomic adds, 1
+        // per-target GEMV, 2 workgroup target tiles
+        D.m2l_mode = P.opt.m2l_tile < 0 ? 1 : P.opt.m2l_tile > 1 ? 2 : P.opt.m2l_tile == 1 ? 0 : 3;
+        if (D.m2l_mode == 3) {
+            // slabs keep the scratch of per-pair results near 1 GiB
+            D.m2ls.resize(nlev);
+            D.m2ms.resize(nlev);
+            D.l2ls.resize(nlev);
+            size_t part = 0, big = 0;
+            auto slabs = [&](const GemvList &G, std::vector<DChunks> &dst) {
+                if (G.out_off.empty()) return;
+                const int64_t max_e = std::max<int64_t>(1, ((int64_t)1 << 30) / (16 * std::max(1, G.rows)));
+                for (const M2LChunks &C : build_chunk_slabs(G, M2LC_CH, max_e)) {
+                    dst.push_back(upload_chunks(D, C));
+                    part = std::max(part, sizeof(double2) * (size_t)C.pr_pos.size() * (size_t)C.s);
+                    big = std::max(big, dst.back().shm);
+                }
+            };
+            for (int l = 0; l < nlev; ++l) {
+                slabs(P.m2l_lists[l], D.m2ls[l]);
+                slabs(P.m2m_lists[l], D.m2ms[l]);
+                slabs(P.l2l_lists[l], D.l2ls[l]);
+                int64_t nch = 0, np = 0;
+                for (const DChunks &c : D.m2ls[l]) nch += c.n, np += c.n_entries;
+                D.tile_stats.push_back({(int64_t)D.m2ls[l].size(), nch, np, 0});
+            }
+            if (big > (size_t)maxsh) throw std::runtime_error("translation operator too large for LDS");
+            if (big > 65536)
+                for (const void *f : {(const void *)k_chunks<TAG_M2L, false, double, true>,
+                                      (const void *)k_chunks<TAG_M2L, false, float, true>,
+                                      (const void *)k_chunks<TAG_M2M, false, double, true>,
+                                      (const void *)k_chunks<TAG_M2M, false, float, true>,
+                                      (const void *)k_chunks<TAG_L2L, true, double, true>,
+                                      (const void *)k_chunks<TAG_L2L, true, float, true>})
+                    HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)big));
+            D.part_bytes = part;
+            if (part) D.part = dalloc<double2>(D, part / sizeof(double2));
+        }
         if (D.m2l_mode == 0) {
             build_m2l_chunks(P, M2LC_CH);
             D.m2lc.resize(nlev);
@@ -817,7 +886,7 @@ void device_upload(Plan &P)
                                         (int64_t)P.m2l_chunks[l].pr_tgt.size(), 0});
                 if (D.m2lc[l].shm > (size_t)maxsh) D.m2l_mode = 1;
                 if (D.m2lc[l].shm > 65536)
-                    HIP_CHECK(hipFuncSetAttribute((const void *)k_chunks<TAG_M2L, false, double>,
+                    HIP_CHECK(hipFuncSetAttribute((const void *)k_chunks<TAG_M2L, false, double, false>,
                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)D.m2lc[l].shm));
             }
             P.m2l_chunks.clear();
@@ -895,7 +964,8 @@ void device_upload(Plan &P)
         D.n_id = P.in_total;
         D.prec = P.opt.precision;
         if (D.prec >= 1) {
-            if (D.m2l_mode != 0) throw std::runtime_error("FP32 far field needs the operator-chunk M2L schedule");
+            if (D.m2l_mode != 0 && D.m2l_mode != 3)
+                throw std::runtime_error("FP32 far field needs the operator-chunk or output-tile schedule");
             std::vector<float2> mf(P.matpool.size()), wf;
             for (size_t i = 0; i < mf.size(); ++i)
                 mf[i] = make_float2((float)P.matpool[i].real(), (float)P.matpool[i].imag());
@@ -998,9 +1068,26 @@ static void launch_chunks(const DChunks &C, int cols, const typename Cx<R>::T *m
 {
     if (!C.n) return;
     const size_t shm = C.shm * sizeof(typename Cx<R>::T) / sizeof(double2);
-    hipLaunchKernelGGL((k_chunks<TAG, TRANS, R>), dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES), dim3(64 * M2LC_WAVES),
-                       shm, st, C.n, C.s, cols, C.rmax, C.ch_mat, C.ch_rank, C.ch_pptr, C.pr_tgt, C.pr_src, mat, in,
-                       out);
+    hipLaunchKernelGGL((k_chunks<TAG, TRANS, R, false>), dim3((C.n + M2LC_WAVES - 1) / M2LC_WAVES),
+                       dim3(64 * M2LC_WAVES), shm, st, C.n, C.s, cols, C.rmax, C.ch_mat, C.ch_rank, C.ch_pptr, C.pr_tgt,
+                       C.pr_src, mat, in, out, (const int64_t *)nullptr, (typename Cx<R>::T *)nullptr);
+}
+
+// partial-sum schedule: per slab, per-pair results into the scratch, then the per-output sums
+template <int TAG, bool TRANS, typename R>
+static void launch_slabs(const std::vector<DChunks> &S, void *part, const typename Cx<R>::T *mat,
+                         const typename Cx<R>::T *in, typename Cx<R>::T *out, hipStream_t st)
+{
+    using C = typename Cx<R>::T;
+    for (const DChunks &c : S) {
+        if (!c.n) continue;
+        const size_t shm = c.shm * sizeof(C) / sizeof(double2);
+        hipLaunchKernelGGL((k_chunks<TAG, TRANS, R, true>), dim3((c.n + M2LC_WAVES - 1) / M2LC_WAVES),
+                           dim3(64 * M2LC_WAVES), shm, st, c.n, c.s, c.cols, c.rmax, c.ch_mat, c.ch_rank, c.ch_pptr,
+                           c.pr_tgt, c.pr_src, mat, in, out, c.pr_pos, (C *)part);
+        hipLaunchKernelGGL((k_seg_sum<R>), dim3((c.n_out + 3) / 4), dim3(256), 0, st, c.n_out, c.s, c.red_out,
+                           c.red_ptr, (const C *)part, out);
+    }
 }
 
 // S2M .. L2T in working precision R (operator-chunk schedule)
@@ -1017,11 +1104,27 @@ static void far_field_chunks(Plan &P, Device &D, const O &c, const typename Cx<R
                            D.s2m.slot, D.s2m.tmpl, D.s2m.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, tW, D.x,
                            D.y, D.z, D.nx, D.ny, D.nz, D.dens, od, P.k, c);
     if (ev) HIP_CHECK(hipEventRecord(ev[3], st));
-    for (int l = D.n_lev - 2; l >= 0; --l) launch_chunks<TAG_M2M, false, R>(D.m2mc[l], D.m2mc[l].cols, mat, od, od, st);
+    const bool slabs = D.m2l_mode == 3;
+    for (int l = D.n_lev - 2; l >= 0; --l) {
+        if (slabs)
+            launch_slabs<TAG_M2M, false, R>(D.m2ms[l], D.part, mat, od, od, st);
+        else
+            launch_chunks<TAG_M2M, false, R>(D.m2mc[l], D.m2mc[l].cols, mat, od, od, st);
+    }
     if (ev) HIP_CHECK(hipEventRecord(ev[4], st));
-    for (int l = 0; l < D.n_lev; ++l) launch_chunks<TAG_M2L, false, R>(D.m2lc[l], D.m2lc[l].s, mat, od, id, st);
+    for (int l = 0; l < D.n_lev; ++l) {
+        if (slabs)
+            launch_slabs<TAG_M2L, false, R>(D.m2ls[l], D.part, mat, od, id, st);
+        else
+            launch_chunks<TAG_M2L, false, R>(D.m2lc[l], D.m2lc[l].s, mat, od, id, st);
+    }
     if (ev) HIP_CHECK(hipEventRecord(ev[5], st));
-    for (int l = 1; l < D.n_lev; ++l) launch_chunks<TAG_L2L, true, R>(D.l2lc[l], D.l2lc[l].cols, mat, id, id, st);
+    for (int l = 1; l < D.n_lev; ++l) {
+        if (slabs)
+            launch_slabs<TAG_L2L, true, R>(D.l2ls[l], D.part, mat, id, id, st);
+        else
+            launch_chunks<TAG_L2L, true, R>(D.l2lc[l], D.l2lc[l].cols, mat, id, id, st);
+    }
     if (ev) HIP_CHECK(hipEventRecord(ev[6], st));
     if (D.l2t.n)
         hipLaunchKernelGGL((k_l2t<R, O>), dim3(D.l2t.n), dim3(LEAF_BLOCK), shm_leaf, st, D.l2t.start, D.l2t.end,
@@ -1052,7 +1155,7 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
         const OpCf cf = {make_float2((float)c.c0.x, (float)c.c0.y), make_float2((float)c.c1.x, (float)c.c1.y),
                          make_float2((float)c.d0.x, (float)c.d0.y), make_float2((float)c.d1.x, (float)c.d1.y)};
         far_field_chunks<float, OpCf>(P, D, cf, D.matf, D.t_Wf, D.odf, D.idf, ev, st);
-    } else if (P.opt.far_field && D.m2l_mode == 0) {
+    } else if (P.opt.far_field && (D.m2l_mode == 0 || D.m2l_mode == 3)) {
         far_field_chunks<double, OpC>(P, D, c, D.mat, D.t_W, D.od, D.id, ev, st);
     } else if (P.opt.far_field) {
         if (D.n_od) hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, D.od, D.n_od);

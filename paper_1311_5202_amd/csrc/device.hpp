@@ -31,6 +31,10 @@ struct DChunks {
     size_t shm = 0;
     int64_t *ch_mat = nullptr, *pr_tgt = nullptr, *pr_src = nullptr;
     int *ch_rank = nullptr, *ch_pptr = nullptr;
+    // partial-sum schedule: per pair its scratch row, per output its entry range
+    int n_out = 0;
+    int64_t n_entries = 0;
+    int64_t *pr_pos = nullptr, *red_out = nullptr, *red_ptr = nullptr;
 };
 
 struct DCorr {
@@ -89,6 +93,10 @@ struct Device {
     std::vector<DTiles> m2lt;          // per level, tiled M2L
     std::vector<DChunks> m2lc;         // per level, operator-chunk M2L
     std::vector<DChunks> m2mc, l2lc;   // per level, operator-chunk M2M and L2L
+    // per level, slabs of the partial-sum schedule (default) and its scratch
+    std::vector<std::vector<DChunks>> m2ls, m2ms, l2ls;
+    void *part = nullptr;
+    size_t part_bytes = 0;
     int m2l_mode = 0;                  // 0 operator chunks, 1 per-target GEMV, 2 target tiles
     double2 *m2l_part = nullptr;       // partial sums of split tiles
     std::vector<std::array<int64_t, 4>> tile_stats;  // per level: tiles, chunks, pairs, segments

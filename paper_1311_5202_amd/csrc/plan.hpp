@@ -124,6 +124,9 @@ struct M2LChunks {
     std::vector<int64_t> ch_mat;
     std::vector<int> ch_rank, ch_pptr;
     std::vector<int64_t> pr_tgt, pr_src;
+    std::vector<int64_t> pr_pos;     // per pair: entry index in the slab (target-major)
+    std::vector<int64_t> red_out;    // per output of the slab: offset
+    std::vector<int64_t> red_ptr;    // per output of the slab: entry range (size n_out+1)
 };
 
 struct LeafTask {
@@ -185,6 +188,11 @@ void build_operators(Plan &P);
 void build_m2l_tiles(Plan &P, int tile, int chunk);
 void build_m2l_chunks(Plan &P, int chunk);
 M2LChunks build_chunks(const GemvList &G, int chunk);
+
+// Chunks over the output range [o0, o1) of a list, with the per-pair results
+// written to a scratch array (entry order of the list, relative to o0) and
+// summed per output in a fixed order afterwards.  Slabs bound the scratch.
+std::vector<M2LChunks> build_chunk_slabs(const GemvList &G, int chunk, int64_t max_entries);
 void correction_table_host(int64_t n_elem, const double *elem, const double *pts, const double *nrm, const double *w,
                            double k, int op, double coupling, std::vector<int64_t> &rp, std::vector<int64_t> &col,
                            std::vector<cplx> &val);

@@ -528,40 +528,66 @@ void build_m2l_tiles(Plan &P, int tile, int chunk)
 
 namespace fdbem {
 
-M2LChunks build_chunks(const GemvList &G, int chunk)
+static M2LChunks build_chunks_range(const GemvList &G, int chunk, int o0, int o1)
 {
     M2LChunks C;
     C.chunk = chunk;
     C.s = G.rows;
     C.cols = G.cols;
     C.trans = G.trans;
-    const int n_out = (int)G.out_off.size();
-    if (n_out == 0) return C;
-    const int64_t ne = (int64_t)G.in_off.size();
+    if (o1 <= o0) return C;
+    const int64_t e0 = G.ptr[o0], e1 = G.ptr[o1], ne = e1 - e0;
     std::vector<int64_t> tgt(ne);
-    for (int o = 0; o < n_out; ++o)
-        for (int e = G.ptr[o]; e < G.ptr[o + 1]; ++e) tgt[e] = G.out_off[o];
+    for (int o = o0; o < o1; ++o) {
+        C.red_out.push_back(G.out_off[o]);
+        C.red_ptr.push_back(G.ptr[o] - e0);
+        for (int e = G.ptr[o]; e < G.ptr[o + 1]; ++e) tgt[e - e0] = G.out_off[o];
+    }
+    C.red_ptr.push_back(ne);
     std::vector<int64_t> idx(ne);
     for (int64_t e = 0; e < ne; ++e) idx[e] = e;
     // by operator, then by target (nearby targets share cache lines)
     std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-        return G.mat_off[a] != G.mat_off[b] ? G.mat_off[a] < G.mat_off[b] : tgt[a] < tgt[b];
+        const int64_t ma = G.mat_off[e0 + a], mb = G.mat_off[e0 + b];
+        return ma != mb ? ma < mb : tgt[a] < tgt[b];
     });
     C.pr_tgt.resize(ne);
     C.pr_src.resize(ne);
+    C.pr_pos.resize(ne);
     for (int64_t q = 0; q < ne; ++q) {
         const int64_t e = idx[q];
-        if (q == 0 || G.mat_off[e] != G.mat_off[idx[q - 1]] || (q - C.ch_pptr.back()) >= chunk) {
-            C.ch_mat.push_back(G.mat_off[e]);
-            C.ch_rank.push_back(G.rank[e]);
+        const int64_t mat = G.mat_off[e0 + e];
+        if (q == 0 || mat != G.mat_off[e0 + idx[q - 1]] || (q - C.ch_pptr.back()) >= chunk) {
+            C.ch_mat.push_back(mat);
+            C.ch_rank.push_back(G.rank[e0 + e]);
             C.ch_pptr.push_back((int)q);
         }
         C.pr_tgt[q] = tgt[e];
-        C.pr_src[q] = G.in_off[e];
+        C.pr_src[q] = G.in_off[e0 + e];
+        C.pr_pos[q] = e;
     }
     C.ch_pptr.push_back((int)ne);
     for (int r : C.ch_rank) C.max_rank = std::max(C.max_rank, r);
     return C;
+}
+
+M2LChunks build_chunks(const GemvList &G, int chunk)
+{
+    return build_chunks_range(G, chunk, 0, (int)G.out_off.size());
+}
+
+std::vector<M2LChunks> build_chunk_slabs(const GemvList &G, int chunk, int64_t max_entries)
+{
+    std::vector<M2LChunks> out;
+    const int n_out = (int)G.out_off.size();
+    int o0 = 0;
+    while (o0 < n_out) {
+        int o1 = o0 + 1;
+        while (o1 < n_out && (int64_t)G.ptr[o1 + 1] - G.ptr[o0] <= max_entries) ++o1;
+        out.push_back(build_chunks_range(G, chunk, o0, o1));
+        o0 = o1;
+    }
+    return out;
 }
 
 void build_m2l_chunks(Plan &P, int chunk)

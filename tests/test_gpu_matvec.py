@@ -92,28 +92,31 @@ def test_fda_high_frequency_sampled_rows(torch):
 
 
 def test_m2l_kernels_agree_and_tiles_are_deterministic(torch):
-    """The three M2L schedules (operator chunks with atomics, per-target GEMV,
-    target tiles) apply the same operators; the tiled one is bitwise
-    reproducible."""
+    """The four translation schedules (operator chunks with per-pair results
+    summed per output, operator chunks with atomic adds, per-target GEMV,
+    workgroup target tiles) apply the same operators; the partial-sum and
+    tiled ones are bitwise reproducible."""
     import paper_1311_5202_amd as fdb
 
     _, pts, nrm, w = _geom(12)
     k = 16.0
     u = torch.from_numpy(synth.random_densities(len(w), 3)).cuda()
     outs = {}
-    for name, tile in (("chunks", 0), ("gemv", -1), ("tiles", 16)):
+    modes = {"partial": 3, "chunks": 0, "gemv": 1, "tiles": 2}
+    for name, tile in (("partial", 0), ("chunks", 1), ("gemv", -1), ("tiles", 16)):
+        print(f"[m2l] schedule {name}", flush=True)
         plan = fdb.build(pts, nrm, w, k, 1e-4, m2l_tile=tile)
-        assert plan.stats()["m2l_mode"] == {"chunks": 0, "gemv": 1, "tiles": 2}[name]
+        assert plan.stats()["m2l_mode"] == modes[name]
         a = plan.matvec(u, "RAW_H").cpu().numpy()
         b = plan.matvec(u, "RAW_H").cpu().numpy()
-        if name == "tiles":
+        if name in ("partial", "tiles"):
             assert np.array_equal(a, b)
         else:
             assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
         outs[name] = a
         plan.close()
     ref = outs["gemv"]
-    for name in ("chunks", "tiles"):
+    for name in ("partial", "chunks", "tiles"):
         assert np.max(np.abs(outs[name] - ref)) <= 1e-12 * np.max(np.abs(ref)), name
 
 
