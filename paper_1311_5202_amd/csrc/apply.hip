@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 
 #include "device.hpp"
 
@@ -528,7 +529,7 @@ __global__ void k_m2l_reduce(int s, int tile, int nseg, const double2 *__restric
 // registers so every operator element read from cache feeds M2LC_CH complex
 // FMAs; sources are staged per wavefront in LDS; results go to the targets
 // with FP64 atomic adds (hardware global_atomic_add_f64).
-constexpr int M2LC_CH = 8;
+constexpr int M2LC_CH = 16;
 constexpr int M2LC_WAVES = 4;
 
 __device__ __forceinline__ void wave_sync()
@@ -616,6 +617,136 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks(int n_chunks, int s,
 
 // Near-field correction, caller order: out_i += sum over the node's element
 // blocks of sum_g val_bg in_{6 e_b + g}.
+// Translation chunks on the matrix cores.  One workgroup (4 wavefronts) per
+// chunk of <= 16 pairs sharing one operator.  The complex product Y = M X
+// (s x cols by cols x 16) is a real product of twice the size with rows
+// (Re y_0, Im y_0, Re y_1, ...) and inner index (Re x_0, Im x_0, ...):
+// A[2i+c][2j+d] = Re M_ij if c == d, -Im M_ij if (c, d) = (0, 1), Im M_ij if
+// (c, d) = (1, 0).  It is evaluated by 16 x 16 x 4 MFMA tiles (16 real rows x
+// 4 inner x 16 pairs): lane l holds A[l%16][l/16] and B[l/16][l%16]; result
+// register q holds D[4q + l/16][l%16] for the FP64 instruction and
+// D[4(l/16) + q][l%16] for the FP32 one.  The sources are staged in LDS in
+// the B layout (inner index major, pair fastest); wavefronts split the row
+// tiles.  Low-rank operators run V then U with T = V X kept in LDS.  Results
+// go to the per-pair scratch (partial-sum schedule).
+constexpr int MF_PAIRS = 16;
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct Mf;
+template <>
+struct Mf<double> {
+    typedef mf_d4 V;
+    static __device__ __forceinline__ V mma(double a, double b, V c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int out_row(int q, int k4) { return 4 * q + k4; }
+};
+template <>
+struct Mf<float> {
+    typedef mf_f4 V;
+    static __device__ __forceinline__ V mma(float a, float b, V c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int out_row(int q, int k4) { return 4 * k4 + q; }
+};
+
+// one real-GEMM sweep over the row tiles: complex A has rows [0, nrow) and
+// inner index [0, ncol); element (row, j) at A + row * rs + j * cs (complex elements)
+template <typename R, typename Store>
+__device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ A, int nrow, int ncol, int64_t rs,
+                                          int64_t cs, const R *__restrict__ B, int wv, int lane, Store store)
+{
+    typedef typename Mf<R>::V V;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int n_rt = (2 * nrow + 15) >> 4, kmax = 2 * ncol;
+    for (int rt = wv; rt < n_rt; rt += M2LC_WAVES) {
+        const int I = rt * 16 + i16, row = I >> 1, ci = I & 1;
+        const bool rok = row < nrow;
+        const R *arow = (const R *)(A + (rok ? row : 0) * rs);
+        V acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        int k0 = 0;
+        for (; k0 + 8 <= kmax; k0 += 8) {
+            const int K0 = k0 + k4, K1 = k0 + 4 + k4;
+            const int j0 = K0 >> 1, d0 = K0 & 1, j1 = K1 >> 1, d1 = K1 & 1;
+            const R x0 = rok ? arow[2 * j0 * cs + (ci ^ d0)] : (R)0;
+            const R x1 = rok ? arow[2 * j1 * cs + (ci ^ d1)] : (R)0;
+            const R a0 = (ci == 0 && d0 == 1) ? -x0 : x0;
+            const R a1 = (ci == 0 && d1 == 1) ? -x1 : x1;
+            const R b0 = B[K0 * MF_PAIRS + i16], b1 = B[K1 * MF_PAIRS + i16];
+            acc0 = Mf<R>::mma(a0, b0, acc0);
+            acc1 = Mf<R>::mma(a1, b1, acc1);
+        }
+        for (; k0 < kmax; k0 += 4) {
+            const int K = k0 + k4, jj = K >> 1, d = K & 1;
+            R a = 0, b = 0;
+            if (K < kmax) {
+                const R x = rok ? arow[2 * jj * cs + (ci ^ d)] : (R)0;
+                a = (ci == 0 && d == 1) ? -x : x;
+                b = B[K * MF_PAIRS + i16];
+            }
+            acc0 = Mf<R>::mma(a, b, acc0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int Io = rt * 16 + Mf<R>::out_row(q, k4);
+            store(Io >> 1, Io & 1, i16, acc0[q] + acc1[q]);
+        }
+    }
+}
+
+template <typename R, bool TRANS>
+__global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, int s, int cols, int rmax,
+                                                                 const int64_t *__restrict__ ch_mat,
+                                                                 const int *__restrict__ ch_rank,
+                                                                 const int *__restrict__ ch_pptr,
+                                                                 const int64_t *__restrict__ pr_src,
+                                                                 const int64_t *__restrict__ pr_pos,
+                                                                 const typename Cx<R>::T *__restrict__ mat,
+                                                                 const typename Cx<R>::T *__restrict__ in,
+                                                                 typename Cx<R>::T *__restrict__ part)
+{
+    using C = typename Cx<R>::T;
+    extern __shared__ unsigned char shraw[];
+    R *XB = (R *)shraw;                            // [2 cols][16]
+    R *TB = XB + (size_t)2 * cols * MF_PAIRS;      // [2 rmax][16]
+    const int c = blockIdx.x;
+    if (c >= n_chunks) return;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int p0 = ch_pptr[c], n = ch_pptr[c + 1] - p0;
+    for (int e = tid; e < MF_PAIRS * cols; e += 64 * M2LC_WAVES) {
+        const int p = e / cols, j = e - p * cols;
+        const C v = p < n ? in[pr_src[p0 + p] + j] : Cx<R>::mk(0, 0);
+        XB[(2 * j) * MF_PAIRS + p] = v.x;
+        XB[(2 * j + 1) * MF_PAIRS + p] = v.y;
+    }
+    __syncthreads();
+    const C *M = mat + ch_mat[c];
+    const int r = ch_rank[c];
+    R *P = (R *)part;
+    auto to_part = [&](int row, int ci, int p, R v) {
+        if (row < s && p < n) P[2 * (pr_pos[p0 + p] * s + row) + ci] = v;
+    };
+    if (r < 0) {
+        // dense s x cols, column-major (or its transpose stored cols x s)
+        if (TRANS)
+            mfma_rows<R>(M, s, cols, (int64_t)cols, 1, XB, wv, lane, to_part);
+        else
+            mfma_rows<R>(M, s, cols, 1, (int64_t)s, XB, wv, lane, to_part);
+    } else {
+        // T = V X (V: r x cols at M + s r, column-major), then Y = U T (U: s x r)
+        auto to_t = [&](int row, int ci, int p, R v) {
+            if (row < r) TB[(2 * row + ci) * MF_PAIRS + p] = v;
+        };
+        mfma_rows<R>(M + (size_t)s * r, r, cols, 1, (int64_t)r, XB, wv, lane, to_t);
+        __syncthreads();
+        mfma_rows<R>(M, s, r, 1, (int64_t)s, TB, wv, lane, to_part);
+    }
+}
+
 // Sum of the per-pair results of each output slot (entries contiguous in
 // target-major order), one wavefront per output, lanes over rows.
 template <typename R>
@@ -726,6 +857,8 @@ static DTiles upload_tiles(Device &D, const M2LTiles &T)
     d.pr_src = dupload(D, T.pr_src);
     return d;
 }
+
+static size_t mfma_shm(const DChunks &c) { return sizeof(double) * 2 * MF_PAIRS * (size_t)(c.cols + c.rmax); }
 
 static DChunks upload_chunks(Device &D, const M2LChunks &C)
 {
@@ -854,7 +987,7 @@ void device_upload(Plan &P)
                 for (const M2LChunks &C : build_chunk_slabs(G, M2LC_CH, max_e)) {
                     dst.push_back(upload_chunks(D, C));
                     part = std::max(part, sizeof(double2) * (size_t)C.pr_pos.size() * (size_t)C.s);
-                    big = std::max(big, dst.back().shm);
+                    big = std::max(big, dst.back().shm / 2);  // FP32 VALU kernel (FP64 runs on MFMA)
                 }
             };
             for (int l = 0; l < nlev; ++l) {
@@ -865,15 +998,16 @@ void device_upload(Plan &P)
                 for (const DChunks &c : D.m2ls[l]) nch += c.n, np += c.n_entries;
                 D.tile_stats.push_back({(int64_t)D.m2ls[l].size(), nch, np, 0});
             }
-            if (big > (size_t)maxsh) throw std::runtime_error("translation operator too large for LDS");
-            if (big > 65536)
-                for (const void *f : {(const void *)k_chunks<TAG_M2L, false, double, true>,
-                                      (const void *)k_chunks<TAG_M2L, false, float, true>,
-                                      (const void *)k_chunks<TAG_M2M, false, double, true>,
-                                      (const void *)k_chunks<TAG_M2M, false, float, true>,
-                                      (const void *)k_chunks<TAG_L2L, true, double, true>,
-                                      (const void *)k_chunks<TAG_L2L, true, float, true>})
-                    HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)big));
+            (void)big;
+            size_t mf = 0;
+            for (auto *v : {&D.m2ls, &D.m2ms, &D.l2ls})
+                for (const auto &lv : *v)
+                    for (const DChunks &c : lv) mf = std::max(mf, mfma_shm(c));
+            if (mf > (size_t)maxsh) throw std::runtime_error("translation operator too large for LDS");
+            if (mf > 65536)
+                for (const void *f : {(const void *)k_chunks_mfma<double, false>, (const void *)k_chunks_mfma<double, true>,
+                                      (const void *)k_chunks_mfma<float, false>, (const void *)k_chunks_mfma<float, true>})
+                    HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mf));
             D.part_bytes = part;
             if (part) D.part = dalloc<double2>(D, part / sizeof(double2));
         }
@@ -1081,10 +1215,9 @@ static void launch_slabs(const std::vector<DChunks> &S, void *part, const typena
     using C = typename Cx<R>::T;
     for (const DChunks &c : S) {
         if (!c.n) continue;
-        const size_t shm = c.shm * sizeof(C) / sizeof(double2);
-        hipLaunchKernelGGL((k_chunks<TAG, TRANS, R, true>), dim3((c.n + M2LC_WAVES - 1) / M2LC_WAVES),
-                           dim3(64 * M2LC_WAVES), shm, st, c.n, c.s, c.cols, c.rmax, c.ch_mat, c.ch_rank, c.ch_pptr,
-                           c.pr_tgt, c.pr_src, mat, in, out, c.pr_pos, (C *)part);
+        hipLaunchKernelGGL((k_chunks_mfma<R, TRANS>), dim3(c.n), dim3(64 * M2LC_WAVES),
+                           mfma_shm(c) * sizeof(R) / sizeof(double), st, c.n, c.s, c.cols, c.rmax, c.ch_mat,
+                           c.ch_rank, c.ch_pptr, c.pr_src, c.pr_pos, mat, in, (C *)part);
         hipLaunchKernelGGL((k_seg_sum<R>), dim3((c.n_out + 3) / 4), dim3(256), 0, st, c.n_out, c.s, c.red_out,
                            c.red_ptr, (const C *)part, out);
     }
