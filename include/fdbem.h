@@ -168,6 +168,32 @@ int fda_set_timing(fda_plan *plan, int on);
  * recorded events, then starts a new averaging window. */
 int fda_phase_times(fda_plan *plan, double *ms, int n);
 
+/* ---- captured mat-vecs and batches of plans ----------------------------
+ * Not steps of the paper's method: ways of launching it.  With graphs on, a
+ * plan captures each (operator, input, output) mat-vec into a HIP graph the
+ * first time and replays it afterwards (bm_solve steps use fixed internal
+ * buffers, so one graph serves a whole solve); at most 8 graphs are kept per
+ * plan.  Results are bitwise those of fda_matvec.  Graphs are bypassed while
+ * fda_set_timing is on. */
+int fda_set_graph(fda_plan *plan, int on);
+
+/* A batch groups plans on the current device (each plan at most once; the
+ * plans must outlive the batch).  fda_batch_matvec applies op to every
+ * instance, in_dev[i] -> out_dev[i] (device complex128 vectors of plan i's
+ * length), as ONE graph launch in which the instances run concurrently on 16
+ * forked streams; the graph is re-captured when op or a pointer changes.
+ * fda_batch_solve runs bm_solve for every instance (op, tol, maxit, restart,
+ * precond as in bm_solve) from a pool of host threads, one stream each, with
+ * graphs on; per-instance iterations, relative residuals and status codes go
+ * to the host arrays iters, relres (may be NULL) and status.  Returns
+ * FDA_NOT_CONVERGED if any instance did not converge.  Synchronous. */
+typedef struct fda_batch fda_batch;
+int fda_batch_create(fda_plan *const *plans, int n, fda_batch **out);
+int fda_batch_matvec(fda_batch *b, int op, const void *const *in_dev, void *const *out_dev, void *hip_stream);
+int fda_batch_solve(fda_batch *b, int op, const void *const *rhs_dev, double tol, int maxit, int restart,
+                    int precond, void *const *x_dev, int *iters, double *relres, int *status);
+void fda_batch_destroy(fda_batch *b);
+
 /* ---- learned coupling correction of the block-Jacobi preconditioner ----
  * Not part of the paper's method: a preconditioner for bm_solve.  Blocks b
  * are the octree leaves cut into pieces of at most 64 points; E_b is the block

@@ -24,7 +24,8 @@ PREC = {"fp64": 0, "fp32": 1, "both": 2}
 EXPORTS = ("fda_default_opts", "bem_nystrom_nodes", "bem_near_correction", "fda_build", "fda_matvec", "bm_solve", "fda_rhs_plane_wave",
            "fda_stats", "fda_set_timing", "fda_phase_times", "fda_destroy", "fda_last_error", "fda_net_num_params",
            "fda_net_create", "fda_net_destroy", "fda_net_get_params", "fda_net_set_params", "fda_net_loss_grad",
-           "fda_net_train_step", "fda_net_attach", "fda_net_loss_grad_raw")
+           "fda_net_train_step", "fda_net_attach", "fda_net_loss_grad_raw", "fda_set_graph", "fda_batch_create",
+           "fda_batch_matvec", "fda_batch_solve", "fda_batch_destroy")
 
 
 class FdaGeometry(ctypes.Structure):
@@ -79,11 +80,17 @@ def lib() -> ctypes.CDLL:
     L.fda_net_train_step.argtypes = [vp, vp, dbl, ctypes.POINTER(dbl)]
     L.fda_net_attach.argtypes = [vp, vp]
     L.fda_net_loss_grad_raw.argtypes = [vp, ci, vp, vp, vp, vp, vp, i64, vp, vp, vp, ctypes.POINTER(dbl), vp]
+    L.fda_set_graph.argtypes = [vp, ci]
+    L.fda_batch_create.argtypes = [vp, ci, ctypes.POINTER(vp)]
+    L.fda_batch_matvec.argtypes = [vp, ci, vp, vp, vp]
+    L.fda_batch_solve.argtypes = [vp, ci, vp, dbl, ci, ci, ci, vp, vp, vp, vp]
+    L.fda_batch_destroy.argtypes = [vp]
+    L.fda_batch_destroy.restype = None
     L.fda_destroy.argtypes = [vp]
     L.fda_destroy.restype = None
     L.fda_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("fda_destroy", "fda_last_error", "fda_net_destroy"):
+        if name not in ("fda_destroy", "fda_last_error", "fda_net_destroy", "fda_batch_destroy"):
             getattr(L, name).restype = ci
     _lib = L
     return L

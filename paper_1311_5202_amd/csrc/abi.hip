@@ -7,6 +7,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <vector>
 
 #include "../../include/fdbem.h"
 #include "device.hpp"
@@ -25,6 +26,11 @@ struct fda_plan {
 
 struct fda_net {
     LearnedNet *N;
+};
+
+struct fda_batch {
+    Batch *B;
+    std::vector<fda_plan *> plans;
 };
 
 static thread_local std::string g_err;
@@ -255,6 +261,79 @@ int fda_phase_times(fda_plan *plan, double *ms, int n)
         for (int t = 0; t < n && t < 8; ++t) ms[t] = plan->P->dev->phase_ms[t];
         return FDA_OK;
     });
+}
+
+int fda_set_graph(fda_plan *plan, int on)
+{
+    return guarded([&] {
+        if (!plan) throw std::invalid_argument("null plan");
+        plan->P->dev->use_graph = on ? 1 : 0;
+        if (!on) graph_release(*plan->P->dev);
+        return FDA_OK;
+    });
+}
+
+int fda_batch_create(fda_plan *const *plans, int n, fda_batch **out)
+{
+    return guarded([&] {
+        if (!plans || !out || n <= 0) throw std::invalid_argument("bad batch arguments");
+        std::vector<Plan *> ps(n);
+        for (int i = 0; i < n; ++i) {
+            if (!plans[i]) throw std::invalid_argument("null plan in batch");
+            ps[i] = plans[i]->P;
+            for (int j = 0; j < i; ++j)
+                if (ps[j] == ps[i]) throw std::invalid_argument("a plan appears twice in the batch");
+        }
+        *out = new fda_batch{batch_create(ps.data(), n), std::vector<fda_plan *>(plans, plans + n)};
+        return FDA_OK;
+    });
+}
+
+int fda_batch_matvec(fda_batch *b, int op, const void *const *in_dev, void *const *out_dev, void *stream)
+{
+    return guarded([&] {
+        if (!b || !in_dev || !out_dev) throw std::invalid_argument("null argument");
+        const int base = op & 0xff;
+        if (base < FDA_OP_RAW_H || base > FDA_OP_BM_G || (op & ~0x1ff)) throw std::invalid_argument("unknown op");
+        for (size_t i = 0; i < b->plans.size(); ++i) {
+            const Plan &P = *b->plans[i]->P;
+            if (!in_dev[i] || !out_dev[i]) throw std::invalid_argument("null vector in batch");
+            if ((op & FDA_OP_FP32) && P.opt.precision == FDA_PREC_FP64)
+                throw std::invalid_argument("FP32 operator requested on an FP64-only plan");
+            if (base >= FDA_OP_BM_H && !P.has_corr) throw std::invalid_argument("BM operator needs elements");
+        }
+        batch_matvec(b->B, op, (const double2 *const *)in_dev, (double2 *const *)out_dev, (hipStream_t)stream);
+        return FDA_OK;
+    });
+}
+
+int fda_batch_solve(fda_batch *b, int op, const void *const *rhs_dev, double tol, int maxit, int restart,
+                    int precond, void *const *x_dev, int *iters, double *relres, int *status)
+{
+    return guarded([&] {
+        if (!b || !rhs_dev || !x_dev || !status) throw std::invalid_argument("null argument");
+        if (!(tol > 0) || maxit <= 0 || restart <= 0) throw std::invalid_argument("bad GMRES parameters");
+        for (size_t i = 0; i < b->plans.size(); ++i) {
+            const Plan &P = *b->plans[i]->P;
+            if (!rhs_dev[i] || !x_dev[i]) throw std::invalid_argument("null vector in batch");
+            if ((op & FDA_OP_FP32) && P.opt.precision == FDA_PREC_FP64)
+                throw std::invalid_argument("FP32 operator requested on an FP64-only plan");
+            if (precond && !P.has_corr) throw std::invalid_argument("preconditioner needs elements");
+        }
+        const int bad = batch_solve(b->B, op, (const double2 *const *)rhs_dev, tol, maxit, restart, precond,
+                                    (double2 *const *)x_dev, iters, relres, status);
+        return bad ? FDA_NOT_CONVERGED : FDA_OK;
+    });
+}
+
+void fda_batch_destroy(fda_batch *b)
+{
+    if (!b) return;
+    try {
+        batch_destroy(b->B);
+    } catch (...) {
+    }
+    delete b;
 }
 
 int fda_net_num_params(void) { return learned_num_params(); }

@@ -667,18 +667,22 @@ __device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ 
         const int I = rt * 16 + i16, row = I >> 1, ci = I & 1;
         const bool rok = row < nrow;
         const R *arow = (const R *)(A + (rok ? row : 0) * rs);
-        V acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+        V acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0}, acc3 = {0, 0, 0, 0};
+        // the inner index of a lane advances by 4 per step: d = k4 & 1 is fixed
+        const int d = k4 & 1;
+        const R sgn = (ci == 0 && d == 1) ? (R)-1 : (R)1;
+        const int sel = ci ^ d;
         int k0 = 0;
-        for (; k0 + 8 <= kmax; k0 += 8) {
-            const int K0 = k0 + k4, K1 = k0 + 4 + k4;
-            const int j0 = K0 >> 1, d0 = K0 & 1, j1 = K1 >> 1, d1 = K1 & 1;
-            const R x0 = rok ? arow[2 * j0 * cs + (ci ^ d0)] : (R)0;
-            const R x1 = rok ? arow[2 * j1 * cs + (ci ^ d1)] : (R)0;
-            const R a0 = (ci == 0 && d0 == 1) ? -x0 : x0;
-            const R a1 = (ci == 0 && d1 == 1) ? -x1 : x1;
-            const R b0 = B[K0 * MF_PAIRS + i16], b1 = B[K1 * MF_PAIRS + i16];
-            acc0 = Mf<R>::mma(a0, b0, acc0);
-            acc1 = Mf<R>::mma(a1, b1, acc1);
+        for (; k0 + 16 <= kmax; k0 += 16) {
+            const int j0 = (k0 + k4) >> 1;
+            R x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = rok ? arow[2 * (j0 + 2 * u) * cs + sel] : (R)0;
+            const R *bp = B + (k0 + k4) * MF_PAIRS + i16;
+            acc0 = Mf<R>::mma(sgn * x[0], bp[0], acc0);
+            acc1 = Mf<R>::mma(sgn * x[1], bp[4 * MF_PAIRS], acc1);
+            acc2 = Mf<R>::mma(sgn * x[2], bp[8 * MF_PAIRS], acc2);
+            acc3 = Mf<R>::mma(sgn * x[3], bp[12 * MF_PAIRS], acc3);
         }
         for (; k0 < kmax; k0 += 4) {
             const int K = k0 + k4, jj = K >> 1, d = K & 1;
@@ -693,7 +697,7 @@ __device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int Io = rt * 16 + Mf<R>::out_row(q, k4);
-            store(Io >> 1, Io & 1, i16, acc0[q] + acc1[q]);
+            store(Io >> 1, Io & 1, i16, (acc0[q] + acc1[q]) + (acc2[q] + acc3[q]));
         }
     }
 }
@@ -748,7 +752,8 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
 }
 
 // Sum of the per-pair results of each output slot (entries contiguous in
-// target-major order), one wavefront per output, lanes over rows.
+// target-major order), one wavefront per output, lanes over rows; four
+// entries in flight per step, added in a fixed order.
 template <typename R>
 __global__ __launch_bounds__(256) void k_seg_sum(int n_out, int s, const int64_t *__restrict__ red_out,
                                                  const int64_t *__restrict__ red_ptr,
@@ -761,9 +766,18 @@ __global__ __launch_bounds__(256) void k_seg_sum(int n_out, int s, const int64_t
     const int64_t e0 = red_ptr[o], e1 = red_ptr[o + 1];
     C *dst = out + red_out[o];
     for (int row = lane; row < s; row += 64) {
-        C a = Cx<R>::mk(0, 0);
-        for (int64_t e = e0; e < e1; ++e) a = cadd(a, part[e * s + row]);
-        dst[row] = cadd(dst[row], a);
+        C a0 = Cx<R>::mk(0, 0), a1 = a0, a2 = a0, a3 = a0;
+        const C *pp = part + e0 * s + row;
+        int64_t e = e0;
+        for (; e + 4 <= e1; e += 4, pp += 4 * (int64_t)s) {
+            const C v0 = pp[0], v1 = pp[s], v2 = pp[2 * (int64_t)s], v3 = pp[3 * (int64_t)s];
+            a0 = cadd(a0, v0);
+            a1 = cadd(a1, v1);
+            a2 = cadd(a2, v2);
+            a3 = cadd(a3, v3);
+        }
+        for (; e < e1; ++e, pp += s) a0 = cadd(a0, pp[0]);
+        dst[row] = cadd(dst[row], cadd(cadd(a0, a1), cadd(a2, a3)));
     }
 }
 
@@ -1135,6 +1149,7 @@ void device_free(Plan &P)
 {
     if (!P.dev) return;
     Device &D = *P.dev;
+    graph_release(D);
     for (void *p : D.allocs) (void)hipFree(p);
     for (void *p : {(void *)D.gm_V, (void *)D.gm_w, (void *)D.gm_r, (void *)D.gm_h, (void *)D.gm_red_c,
                     (void *)D.gm_z, (void *)D.gm_t})

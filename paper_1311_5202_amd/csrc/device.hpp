@@ -117,6 +117,16 @@ struct Device {
     int gm_m = 0;
     double2 *gm_V = nullptr, *gm_w = nullptr, *gm_x = nullptr, *gm_r = nullptr, *gm_h = nullptr;
     double2 *gm_red_c = nullptr;
+    // mat-vecs replayed from captured HIP graphs (keyed by operator and buffers)
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        int op = 0;
+        const void *in = nullptr;
+        void *out = nullptr;
+    };
+    int use_graph = 0;
+    hipStream_t cap = nullptr;
+    std::vector<GraphEntry> graphs;
     // timing
     int timing = 0;
     static constexpr int kRing = 64;     // timed mat-vecs kept for averaging
@@ -150,6 +160,16 @@ double learned_loss_grad_raw(LearnedNet *N, int nb, const int64_t *poff, const i
                              const int64_t *boff, const int64_t *toff, int64_t n_rows, const double *F,
                              const double2 *Binv, const double2 *T);
 void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st);
+// device_matvec through a captured graph when the plan has graphs enabled
+void graph_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st);
+void graph_release(Device &D);
+
+struct Batch;
+Batch *batch_create(Plan *const *plans, int n);
+void batch_destroy(Batch *B);
+void batch_matvec(Batch *B, int op, const double2 *const *in, double2 *const *out, hipStream_t st);
+int batch_solve(Batch *B, int op, const double2 *const *rhs, double tol, int maxit, int restart, int precond,
+                double2 *const *x, int *iters, double *relres, int *status);
 void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t st);
 int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int restart, int precond, double2 *x,
                  int *iters, double *relres, double *hist, hipStream_t st);

@@ -168,7 +168,7 @@ int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int r
     if (precond == 2 && (!D.bj.O || D.bj.rank == 0)) return -7;
     if (precond == 3) learned_targets(P);
     const int m = std::max(1, std::min(restart, maxit));
-    if (precond && !D.gm_z) {
+    if ((precond || D.use_graph) && !D.gm_z) {
         HIP_CHECK(hipMalloc(&D.gm_z, sizeof(double2) * n));
         HIP_CHECK(hipMalloc(&D.gm_t, sizeof(double2) * n));
     }
@@ -212,7 +212,11 @@ int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int r
             double2 *vj = D.gm_V + (int64_t)j * n;
             if (precond) {
                 apply_block_jacobi(P, vj, D.gm_z, st, precond);
-                device_matvec(P, op, D.gm_z, D.gm_w, st);
+                graph_matvec(P, op, D.gm_z, D.gm_w, st);
+            } else if (D.use_graph) {
+                // fixed buffers so one captured graph serves every step
+                hipLaunchKernelGGL(k_scale_copy, dim3(g), dim3(256), 0, st, vj, 1.0, D.gm_z, n);
+                graph_matvec(P, op, D.gm_z, D.gm_w, st);
             } else
                 device_matvec(P, op, vj, D.gm_w, st);
             // CGS with one re-orthogonalisation
@@ -281,7 +285,7 @@ int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int r
         } else
             hipLaunchKernelGGL(k_add_combo, dim3(g), dim3(256), 0, st, D.gm_V, n, D.gm_h, j, x, n);
         // true residual
-        device_matvec(P, op, x, D.gm_w, st);
+        graph_matvec(P, op, x, D.gm_w, st);
         hipLaunchKernelGGL(k_sub, dim3(g), dim3(256), 0, st, b, D.gm_w, D.gm_r, n);
         beta = W.norm(D.gm_r);
         rel = beta / bnorm;

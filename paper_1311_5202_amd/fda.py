@@ -138,6 +138,10 @@ class Plan:
             _abi.check(rc)
         return x, info
 
+    def set_graph(self, on: bool = True):
+        """Replay mat-vecs (and bm_solve steps) from captured HIP graphs."""
+        _abi.check(_abi.lib().fda_set_graph(self._h, 1 if on else 0))
+
     def set_timing(self, on: bool = True):
         _abi.check(_abi.lib().fda_set_timing(self._h, 1 if on else 0))
 
@@ -155,6 +159,62 @@ class Plan:
 
 def build(pts, nrm, w, k, eps, elements=None, **opts) -> Plan:
     return Plan(pts, nrm, w, k, eps, elements=elements, **opts)
+
+
+class Batch:
+    """Many plans applied in one graph launch (fda_batch_*); the plans must
+    stay alive while the batch exists."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _abi.check(_abi.lib().fda_batch_create(arr, len(self.plans), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _abi.lib().fda_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, vecs):
+        if len(vecs) != len(self.plans):
+            raise ValueError("one vector per plan")
+        for v, p in zip(vecs, self.plans):
+            _check_vec(v, p.n)
+        return (ctypes.c_void_p * len(vecs))(*[v.data_ptr() for v in vecs])
+
+    def matvec(self, us, op: str = "BM_H", outs=None, stream=None, fp32: bool = False):
+        import torch
+
+        if outs is None:
+            outs = [torch.empty_like(u) for u in us]
+        _abi.check(_abi.lib().fda_batch_matvec(self._h, Plan._op(op, fp32), self._ptrs(us), self._ptrs(outs),
+                                               _stream_ptr(stream)))
+        return outs
+
+    def solve(self, rhs, tol: float, maxit: int = 200, restart: int = 200, op: str = "BM_H", precond: int = 0,
+              fp32: bool = False, raise_on_fail: bool = True):
+        import torch
+
+        xs = [torch.empty_like(b) for b in rhs]
+        n = len(self.plans)
+        it = (ctypes.c_int * n)()
+        rr = (ctypes.c_double * n)()
+        stt = (ctypes.c_int * n)()
+        torch.cuda.synchronize()
+        rc = _abi.lib().fda_batch_solve(self._h, Plan._op(op, fp32), self._ptrs(rhs), float(tol), int(maxit),
+                                        int(restart), int(precond), self._ptrs(xs), it, rr, stt)
+        info = {"status": rc, "iterations": list(it), "relres": list(rr), "instance_status": list(stt)}
+        if rc != _abi.FDA_OK and raise_on_fail:
+            _abi.check(rc)
+        return xs, info
 
 
 class Net:
