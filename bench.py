@@ -28,6 +28,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# batched workload: uneven instances (sphere / ellipsoid / star), N ~ U[10k, 100k],
+# kD ~ U[5, 60], FP32 far and near field, all instances in one graph launch
+BATCH = {"c3": (64, 2, (10_000, 100_000), (5.0, 60.0))}
+
 WORKLOADS = {
     # name: (octahedral split n, k, eps, description)
     "c1": (8, 5.0, 1e-4, "unit sphere, 512 quadratic triangles, N=3072, k=5 (kD=10), eps=1e-4"),
@@ -131,12 +135,80 @@ def gmres_compare(fdb, synth, plan, tol: float, coupling: float, epochs: int, lo
     return out
 
 
+def batch_main(args, fdb, synth, torch) -> int:
+    """Uneven instances: one graph launch applies every instance's FP32
+    mat-vec; compared with the same mat-vecs launched one plan at a time."""
+    count, seed, n_range, kd_range = BATCH[args.workload]
+    count = args.instances or count
+    plans = []
+    t0 = time.perf_counter()
+    for el, k, kind in synth.instance_batch(count, seed, n_range=n_range, kd_range=kd_range):
+        pts, nrm, w = fdb.nystrom_nodes(el)
+        plans.append(fdb.build(pts, nrm, w, k, 1e-4, elements=el, corrections=1, precision="both",
+                               coupling=args.coupling))
+        print(f"[bench] instance {len(plans)}/{count}: {kind} N={len(w)} k={k:.1f}", file=sys.stderr, flush=True)
+    t_build = time.perf_counter() - t0
+    n_tot = sum(p.n for p in plans)
+    us = [torch.from_numpy(synth.random_densities(p.n, i)).cuda() for i, p in enumerate(plans)]
+    outs = [torch.empty_like(u) for u in us]
+    batch = fdb.Batch(plans)
+
+    def run_batched():
+        batch.matvec(us, "BM_H", outs=outs, fp32=True)
+
+    def run_sequential():
+        for p, u, o in zip(plans, us, outs):
+            p.matvec(u, "BM_H", out=o, fp32=True)
+
+    res = {}
+    for name, fn in (("sequential", run_sequential), ("batched", run_batched)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / args.steps
+        print(f"[bench] {name}: {1e3 * res[name]:.2f} ms per pass over {count} instances", file=sys.stderr,
+              flush=True)
+    dt = res["batched"]
+    out = {
+        "metric": "FDA instance mat-vecs/s (uneven batch, one graph launch)",
+        "value": count / dt,
+        "unit": "instance-matvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{count} instances (sphere/ellipsoid/star), N~U{list(n_range)}, "
+                               f"kD~U{list(kd_range)}, eps=1e-4, BM_H, FP32 far and near field",
+                   "total_N": n_tot, "alpha": f"{args.coupling:g}i/k", "parallelism": "single GPU"},
+        "sequential_ms_per_step": 1e3 * res["sequential"],
+        "speedup_vs_sequential_launches": res["sequential"] / dt,
+        "build_s": t_build,
+        "roofline": None,
+    }
+    batch.close()
+    for p in plans:
+        p.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=os.environ.get("FDBEM_WORKLOAD", "c5"), choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=os.environ.get("FDBEM_WORKLOAD", "c5"),
+                    choices=sorted(WORKLOADS) + sorted(BATCH))
+    ap.add_argument("--instances", type=int, default=0, help="batched workload: number of instances (0: 64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0)
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES time-to-tolerance comparison")
@@ -162,6 +234,8 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload in BATCH:
+        return batch_main(args, fdb, synth, torch)
     n_split, k, eps, desc = WORKLOADS[args.workload]
     el = synth.octa_sphere(n_split)
     pts, nrm, w = fdb.nystrom_nodes(el)

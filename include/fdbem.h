@@ -96,6 +96,8 @@ typedef struct {
     double coupling;    /* Burton-Miller coupling alpha = i * coupling / k (section 2.1,
                            eq. eq_bm); 0 -> 1, the value the paper uses.  -1 gives the
                            conjugate coupling (see bm_solve). */
+    int autotune;       /* 1 (default): at build, time 16 and 32 pairs per M2L chunk on the
+                           plan's own lists and keep the faster per level; 0: 16 */
 } fda_opts;
 
 typedef struct fda_plan fda_plan;

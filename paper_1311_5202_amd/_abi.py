@@ -39,7 +39,8 @@ class FdaOpts(ctypes.Structure):
                 ("lf_grid", ctypes.c_int), ("precision", ctypes.c_int), ("corrections", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("wedge_factor", ctypes.c_int), ("m2l_tile", ctypes.c_int),
                 ("p2p_threshold", ctypes.c_double),
-                ("coupling", ctypes.c_double)]
+                ("coupling", ctypes.c_double),
+                ("autotune", ctypes.c_int)]
 
 
 class FdaError(RuntimeError):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -82,6 +83,7 @@ int fda_default_opts(fda_opts *o)
     o->m2l_tile = 0;
     o->p2p_threshold = 0;
     o->coupling = 1.0;
+    o->autotune = 1;
     return FDA_OK;
 }
 
@@ -138,6 +140,7 @@ int fda_build(const fda_geometry *g, double k, double eps, const fda_opts *o, fd
             if (o->p2p_threshold != 0) opt.p2p_threshold = o->p2p_threshold;
             if (!std::isfinite(o->coupling)) throw std::invalid_argument("non-finite coupling");
             opt.coupling = o->coupling != 0 ? o->coupling : 1.0;
+            opt.autotune = o->autotune;
         }
         if (opt.precision < FDA_PREC_FP64 || opt.precision > FDA_PREC_BOTH) throw std::invalid_argument("unknown precision");
         if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");
@@ -225,6 +228,15 @@ int fda_stats(const fda_plan *plan, char *buf, size_t len)
                 if (T.n_tiles) tile = T.tile, chunk = T.chunk, shm = std::max(shm, T.shm);
             int maxsh = 0;
             (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, P.dev->device);
+            s += ", \"m2l_autotune\": [";
+            for (size_t q = 0; q < P.dev->autotune.size(); ++q) {
+                const auto &a = P.dev->autotune[q];
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "%s{\"level\": %d, \"pairs_per_chunk\": %d, \"ms_16\": %.4f, \"ms_32\": %.4f}",
+                              q ? ", " : "", (int)a[0], (int)a[1], a[2], a[3]);
+                s += buf;
+            }
+            s += "]";
             s += ", \"m2l_mode\": " + std::to_string(P.dev->m2l_mode) + ", \"m2l_tile\": " + std::to_string(tile) +
                  ", \"m2l_chunk\": " + std::to_string(chunk) + ", \"m2l_lds_bytes\": " + std::to_string(shm) +
                  ", \"max_lds_per_block\": " + std::to_string(maxsh) + ", \"m2l_tiles\": [";

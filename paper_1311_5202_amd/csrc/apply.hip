@@ -14,6 +14,7 @@
 //   un-permute, free term, near-field correction SpMV (caller order)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -630,6 +631,7 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks(int n_chunks, int s,
 // tiles.  Low-rank operators run V then U with T = V X kept in LDS.  Results
 // go to the per-pair scratch (partial-sum schedule).
 constexpr int MF_PAIRS = 16;
+constexpr int kXcds = 8;  // accelerator complex dies of the MI355X
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 
@@ -655,54 +657,71 @@ struct Mf<float> {
 };
 
 // one real-GEMM sweep over the row tiles: complex A has rows [0, nrow) and
-// inner index [0, ncol); element (row, j) at A + row * rs + j * cs (complex elements)
-template <typename R, typename Store>
+// inner index [0, ncol); element (row, j) at A + row * rs + j * cs (complex
+// elements); B holds NT tiles of 16 pairs (row stride 16 NT), and every A
+// element loaded feeds NT matrix-core products.  The inner index is split
+// into the same four interleaved partial sums for every NT, so a pair's
+// result does not depend on NT bit for bit.
+template <typename R, int NT, typename Store>
 __device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ A, int nrow, int ncol, int64_t rs,
                                           int64_t cs, const R *__restrict__ B, int wv, int lane, Store store)
 {
     typedef typename Mf<R>::V V;
+    constexpr int PW = 16 * NT, U = 4;
     const int i16 = lane & 15, k4 = lane >> 4;
     const int n_rt = (2 * nrow + 15) >> 4, kmax = 2 * ncol;
     for (int rt = wv; rt < n_rt; rt += M2LC_WAVES) {
         const int I = rt * 16 + i16, row = I >> 1, ci = I & 1;
         const bool rok = row < nrow;
         const R *arow = (const R *)(A + (rok ? row : 0) * rs);
-        V acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0}, acc3 = {0, 0, 0, 0};
+        V acc[U][NT];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[u][t] = V{0, 0, 0, 0};
         // the inner index of a lane advances by 4 per step: d = k4 & 1 is fixed
         const int d = k4 & 1;
         const R sgn = (ci == 0 && d == 1) ? (R)-1 : (R)1;
         const int sel = ci ^ d;
         int k0 = 0;
-        for (; k0 + 16 <= kmax; k0 += 16) {
+        for (; k0 + 4 * U <= kmax; k0 += 4 * U) {
             const int j0 = (k0 + k4) >> 1;
-            R x[4];
+            R x[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) x[u] = rok ? arow[2 * (j0 + 2 * u) * cs + sel] : (R)0;
-            const R *bp = B + (k0 + k4) * MF_PAIRS + i16;
-            acc0 = Mf<R>::mma(sgn * x[0], bp[0], acc0);
-            acc1 = Mf<R>::mma(sgn * x[1], bp[4 * MF_PAIRS], acc1);
-            acc2 = Mf<R>::mma(sgn * x[2], bp[8 * MF_PAIRS], acc2);
-            acc3 = Mf<R>::mma(sgn * x[3], bp[12 * MF_PAIRS], acc3);
+            for (int u = 0; u < U; ++u) x[u] = rok ? arow[2 * (j0 + 2 * u) * cs + sel] : (R)0;
+            const R *bp = B + (k0 + k4) * PW + i16;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[u][t] = Mf<R>::mma(sgn * x[u], bp[4 * u * PW + 16 * t], acc[u][t]);
         }
         for (; k0 < kmax; k0 += 4) {
-            const int K = k0 + k4, jj = K >> 1, d = K & 1;
-            R a = 0, b = 0;
+            const int K = k0 + k4, jj = K >> 1, dd = K & 1;
+            R a = 0;
             if (K < kmax) {
-                const R x = rok ? arow[2 * jj * cs + (ci ^ d)] : (R)0;
-                a = (ci == 0 && d == 1) ? -x : x;
-                b = B[K * MF_PAIRS + i16];
+                const R x = rok ? arow[2 * jj * cs + (ci ^ dd)] : (R)0;
+                a = (ci == 0 && dd == 1) ? -x : x;
             }
-            acc0 = Mf<R>::mma(a, b, acc0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const R b = K < kmax ? B[K * PW + 16 * t + i16] : (R)0;
+                acc[0][t] = Mf<R>::mma(a, b, acc[0][t]);
+            }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int Io = rt * 16 + Mf<R>::out_row(q, k4);
-            store(Io >> 1, Io & 1, i16, (acc0[q] + acc1[q]) + (acc2[q] + acc3[q]));
-        }
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                R v = 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) v += acc[u][t][q];
+                const int Io = rt * 16 + Mf<R>::out_row(q, k4);
+                store(Io >> 1, Io & 1, 16 * t + i16, v);
+            }
     }
 }
 
-template <typename R, bool TRANS>
+template <typename R, bool TRANS, int NT>
 __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, int s, int cols, int rmax,
                                                                  const int64_t *__restrict__ ch_mat,
                                                                  const int *__restrict__ ch_rank,
@@ -714,18 +733,23 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
                                                                  typename Cx<R>::T *__restrict__ part)
 {
     using C = typename Cx<R>::T;
+    constexpr int PW = 16 * NT;
     extern __shared__ unsigned char shraw[];
-    R *XB = (R *)shraw;                            // [2 cols][16]
-    R *TB = XB + (size_t)2 * cols * MF_PAIRS;      // [2 rmax][16]
-    const int c = blockIdx.x;
+    R *XB = (R *)shraw;                        // [2 cols][PW]
+    R *TB = XB + (size_t)2 * cols * PW;        // [2 rmax][PW]
+    // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so XCD
+    // x takes the contiguous chunk range [x per, (x + 1) per); chunks of one
+    // operator are adjacent and reuse that XCD's L2
+    const int per = (n_chunks + kXcds - 1) / kXcds;
+    const int c = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
     if (c >= n_chunks) return;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int p0 = ch_pptr[c], n = ch_pptr[c + 1] - p0;
-    for (int e = tid; e < MF_PAIRS * cols; e += 64 * M2LC_WAVES) {
+    for (int e = tid; e < PW * cols; e += 64 * M2LC_WAVES) {
         const int p = e / cols, j = e - p * cols;
         const C v = p < n ? in[pr_src[p0 + p] + j] : Cx<R>::mk(0, 0);
-        XB[(2 * j) * MF_PAIRS + p] = v.x;
-        XB[(2 * j + 1) * MF_PAIRS + p] = v.y;
+        XB[(2 * j) * PW + p] = v.x;
+        XB[(2 * j + 1) * PW + p] = v.y;
     }
     __syncthreads();
     const C *M = mat + ch_mat[c];
@@ -737,17 +761,17 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
     if (r < 0) {
         // dense s x cols, column-major (or its transpose stored cols x s)
         if (TRANS)
-            mfma_rows<R>(M, s, cols, (int64_t)cols, 1, XB, wv, lane, to_part);
+            mfma_rows<R, NT>(M, s, cols, (int64_t)cols, 1, XB, wv, lane, to_part);
         else
-            mfma_rows<R>(M, s, cols, 1, (int64_t)s, XB, wv, lane, to_part);
+            mfma_rows<R, NT>(M, s, cols, 1, (int64_t)s, XB, wv, lane, to_part);
     } else {
         // T = V X (V: r x cols at M + s r, column-major), then Y = U T (U: s x r)
         auto to_t = [&](int row, int ci, int p, R v) {
-            if (row < r) TB[(2 * row + ci) * MF_PAIRS + p] = v;
+            if (row < r) TB[(2 * row + ci) * PW + p] = v;
         };
-        mfma_rows<R>(M + (size_t)s * r, r, cols, 1, (int64_t)r, XB, wv, lane, to_t);
+        mfma_rows<R, NT>(M + (size_t)s * r, r, cols, 1, (int64_t)r, XB, wv, lane, to_t);
         __syncthreads();
-        mfma_rows<R>(M, s, r, 1, (int64_t)s, TB, wv, lane, to_part);
+        mfma_rows<R, NT>(M, s, r, 1, (int64_t)s, TB, wv, lane, to_part);
     }
 }
 
@@ -813,6 +837,8 @@ __global__ void k_plane_wave(const double *__restrict__ X, const double *__restr
 }
 
 // ---------------------------------------------------------------- host side
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
 template <typename T>
 static T *dalloc(Device &D, size_t n)
 {
@@ -872,7 +898,13 @@ static DTiles upload_tiles(Device &D, const M2LTiles &T)
     return d;
 }
 
-static size_t mfma_shm(const DChunks &c) { return sizeof(double) * 2 * MF_PAIRS * (size_t)(c.cols + c.rmax); }
+// pairs per slab: the scratch of per-pair results stays near 1 GiB
+static int64_t slab_entries(const GemvList &G)
+{
+    return std::max<int64_t>(1, ((int64_t)1 << 30) / (16 * std::max(1, G.rows)));
+}
+
+static size_t mfma_shm(const DChunks &c) { return sizeof(double) * 2 * c.pw * (size_t)(c.cols + c.rmax); }
 
 static DChunks upload_chunks(Device &D, const M2LChunks &C)
 {
@@ -888,6 +920,7 @@ static DChunks upload_chunks(Device &D, const M2LChunks &C)
     d.ch_pptr = dupload(D, C.ch_pptr);
     d.pr_tgt = dupload(D, C.pr_tgt);
     d.pr_src = dupload(D, C.pr_src);
+    d.pw = C.chunk;
     if (!C.red_out.empty()) {
         d.n_out = (int)C.red_out.size();
         d.n_entries = (int64_t)C.pr_pos.size();
@@ -921,6 +954,74 @@ static DLeaf upload_leaf(Device &D, const Plan &P, const std::vector<LeafTask> &
     L.tmpl = dupload(D, tm);
     L.center = dupload(D, c);
     return L;
+}
+
+template <int TAG, bool TRANS, typename R>
+static void launch_slabs(const std::vector<DChunks> &S, void *part, const typename Cx<R>::T *mat,
+                         const typename Cx<R>::T *in, typename Cx<R>::T *out, hipStream_t st);
+
+static void free_chunks(Device &D, DChunks &c)
+{
+    for (void *p : {(void *)c.ch_mat, (void *)c.pr_tgt, (void *)c.pr_src, (void *)c.ch_rank, (void *)c.ch_pptr,
+                    (void *)c.pr_pos, (void *)c.red_out, (void *)c.red_ptr}) {
+        if (!p) continue;
+        auto it = std::find(D.allocs.begin(), D.allocs.end(), p);
+        if (it != D.allocs.end()) D.allocs.erase(it);
+        (void)hipFree(p);
+    }
+    c = DChunks();
+}
+
+// Builder autotuner: for every M2L level, time the matrix-core chunk kernel
+// with 16 and with 32 pairs per chunk (one or two pair tiles per operator
+// element loaded) on this plan's own lists and keep the faster.  Both shapes
+// give bitwise the same result.
+static void autotune_m2l(Plan &P, Device &D)
+{
+    const bool f32 = D.prec == 1;
+    if (f32) {
+        hipLaunchKernelGGL(k_fill_zero<float2>, dim3(nblk(D.n_od, 256)), dim3(256), 0, 0, D.odf, D.n_od);
+        hipLaunchKernelGGL(k_fill_zero<float2>, dim3(nblk(D.n_id, 256)), dim3(256), 0, 0, D.idf, D.n_id);
+    } else {
+        hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_od, 256)), dim3(256), 0, 0, D.od, D.n_od);
+        hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_id, 256)), dim3(256), 0, 0, D.id, D.n_id);
+    }
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    auto time = [&](const std::vector<DChunks> &S) {
+        float best = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+            HIP_CHECK(hipEventRecord(e0, 0));
+            if (f32)
+                launch_slabs<TAG_M2L, false, float>(S, D.part, D.matf, D.odf, D.idf, 0);
+            else
+                launch_slabs<TAG_M2L, false, double>(S, D.part, D.mat, D.od, D.id, 0);
+            HIP_CHECK(hipEventRecord(e1, 0));
+            HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) best = std::min(best, ms);
+        }
+        return (double)best;
+    };
+    for (int l = 0; l < (int)D.m2ls.size(); ++l) {
+        if (D.m2ls[l].empty()) continue;
+        const GemvList &G = P.m2l_lists[l];
+        std::vector<DChunks> alt;
+        for (const M2LChunks &C : build_chunk_slabs(G, 2 * M2LC_CH, slab_entries(G))) alt.push_back(upload_chunks(D, C));
+        const double t16 = time(D.m2ls[l]), t32 = time(alt);
+        const bool take = t32 < t16;
+        if (take) std::swap(D.m2ls[l], alt);
+        for (DChunks &c : alt) free_chunks(D, c);
+        D.autotune.push_back({(double)l, (double)(take ? 2 * M2LC_CH : M2LC_CH), t16, t32});
+        if (P.opt.verbose) {
+            std::fprintf(stderr, "[fdbem] autotune M2L level %d: 16 pairs %.3f ms, 32 pairs %.3f ms\n", l, t16, t32);
+            std::fflush(stderr);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
 }
 
 void device_upload(Plan &P)
@@ -997,8 +1098,7 @@ void device_upload(Plan &P)
             size_t part = 0, big = 0;
             auto slabs = [&](const GemvList &G, std::vector<DChunks> &dst) {
                 if (G.out_off.empty()) return;
-                const int64_t max_e = std::max<int64_t>(1, ((int64_t)1 << 30) / (16 * std::max(1, G.rows)));
-                for (const M2LChunks &C : build_chunk_slabs(G, M2LC_CH, max_e)) {
+                for (const M2LChunks &C : build_chunk_slabs(G, M2LC_CH, slab_entries(G))) {
                     dst.push_back(upload_chunks(D, C));
                     part = std::max(part, sizeof(double2) * (size_t)C.pr_pos.size() * (size_t)C.s);
                     big = std::max(big, dst.back().shm / 2);  // FP32 VALU kernel (FP64 runs on MFMA)
@@ -1019,8 +1119,11 @@ void device_upload(Plan &P)
                     for (const DChunks &c : lv) mf = std::max(mf, mfma_shm(c));
             if (mf > (size_t)maxsh) throw std::runtime_error("translation operator too large for LDS");
             if (mf > 65536)
-                for (const void *f : {(const void *)k_chunks_mfma<double, false>, (const void *)k_chunks_mfma<double, true>,
-                                      (const void *)k_chunks_mfma<float, false>, (const void *)k_chunks_mfma<float, true>})
+                for (const void *f :
+                     {(const void *)k_chunks_mfma<double, false, 1>, (const void *)k_chunks_mfma<double, true, 1>,
+                      (const void *)k_chunks_mfma<float, false, 1>, (const void *)k_chunks_mfma<float, true, 1>,
+                      (const void *)k_chunks_mfma<double, false, 2>, (const void *)k_chunks_mfma<double, true, 2>,
+                      (const void *)k_chunks_mfma<float, false, 2>, (const void *)k_chunks_mfma<float, true, 2>})
                     HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mf));
             D.part_bytes = part;
             if (part) D.part = dalloc<double2>(D, part / sizeof(double2));
@@ -1143,6 +1246,7 @@ void device_upload(Plan &P)
     }
     D.ev.assign((size_t)Device::kRing * 10, nullptr);
     for (auto &e : D.ev) HIP_CHECK(hipEventCreate(&e));
+    if (P.opt.autotune && P.opt.far_field && D.m2l_mode == 3) autotune_m2l(P, D);
 }
 
 void device_free(Plan &P)
@@ -1183,7 +1287,6 @@ static OpC op_coef(int op, double ka)
     return c;
 }
 
-static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <int TAG>
 static void run_gemv(const DGemv &g, const double2 *mat, const double2 *in, double2 *out, hipStream_t st)
@@ -1230,9 +1333,14 @@ static void launch_slabs(const std::vector<DChunks> &S, void *part, const typena
     using C = typename Cx<R>::T;
     for (const DChunks &c : S) {
         if (!c.n) continue;
-        hipLaunchKernelGGL((k_chunks_mfma<R, TRANS>), dim3(c.n), dim3(64 * M2LC_WAVES),
-                           mfma_shm(c) * sizeof(R) / sizeof(double), st, c.n, c.s, c.cols, c.rmax, c.ch_mat,
-                           c.ch_rank, c.ch_pptr, c.pr_src, c.pr_pos, mat, in, (C *)part);
+        const size_t shm = mfma_shm(c) * sizeof(R) / sizeof(double);
+        const unsigned grid = (unsigned)(((c.n + kXcds - 1) / kXcds) * kXcds);
+        if (c.pw == 32)
+            hipLaunchKernelGGL((k_chunks_mfma<R, TRANS, 2>), dim3(grid), dim3(64 * M2LC_WAVES), shm, st, c.n, c.s,
+                               c.cols, c.rmax, c.ch_mat, c.ch_rank, c.ch_pptr, c.pr_src, c.pr_pos, mat, in, (C *)part);
+        else
+            hipLaunchKernelGGL((k_chunks_mfma<R, TRANS, 1>), dim3(grid), dim3(64 * M2LC_WAVES), shm, st, c.n, c.s,
+                               c.cols, c.rmax, c.ch_mat, c.ch_rank, c.ch_pptr, c.pr_src, c.pr_pos, mat, in, (C *)part);
         hipLaunchKernelGGL((k_seg_sum<R>), dim3((c.n_out + 3) / 4), dim3(256), 0, st, c.n_out, c.s, c.red_out,
                            c.red_ptr, (const C *)part, out);
     }

@@ -32,7 +32,7 @@ struct DChunks {
     int64_t *ch_mat = nullptr, *pr_tgt = nullptr, *pr_src = nullptr;
     int *ch_rank = nullptr, *ch_pptr = nullptr;
     // partial-sum schedule: per pair its scratch row, per output its entry range
-    int n_out = 0;
+    int n_out = 0, pw = 16;          // pw: pairs per chunk (16 or 32)
     int64_t n_entries = 0;
     int64_t *pr_pos = nullptr, *red_out = nullptr, *red_ptr = nullptr;
 };
@@ -125,6 +125,7 @@ struct Device {
         void *out = nullptr;
     };
     int use_graph = 0;
+    std::vector<std::array<double, 4>> autotune;   // per tuned level: level, pairs per chunk, ms(16), ms(32)
     hipStream_t cap = nullptr;
     std::vector<GraphEntry> graphs;
     // timing

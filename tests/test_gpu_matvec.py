@@ -176,3 +176,23 @@ def test_table1_accuracy_against_paper(torch, eps):
     print(f"[table1] eps_a {err:.3e} (paper improved {ref_eps_a:.2e})", flush=True)
     assert err <= 2 * ref_eps_a
     plan.close()
+
+
+def test_autotuned_chunk_shapes_give_identical_results(torch):
+    """The builder's M2L autotuner picks 16 or 32 pairs per chunk per level;
+    either shape gives bitwise the same mat-vec, and the choice is reported."""
+    import paper_1311_5202_amd as fdb
+
+    _, pts, nrm, w = _geom(16)
+    k = 24.0
+    u = torch.from_numpy(synth.random_densities(len(w), 5)).cuda()
+    ref_plan = fdb.build(pts, nrm, w, k, 1e-4, autotune=0)
+    ref = ref_plan.matvec(u, "RAW_H")
+    assert ref_plan.stats()["m2l_autotune"] == []
+    ref_plan.close()
+    plan = fdb.build(pts, nrm, w, k, 1e-4, autotune=1)
+    tuned = plan.stats()["m2l_autotune"]
+    print("[autotune]", tuned, flush=True)
+    assert tuned and all(t["pairs_per_chunk"] in (16, 32) for t in tuned)
+    assert torch.equal(plan.matvec(u, "RAW_H"), ref)
+    plan.close()
