@@ -658,7 +658,7 @@ struct Mf<float> {
 
 // one real-GEMM sweep over the row tiles: complex A has rows [0, nrow) and
 // inner index [0, ncol); element (row, j) at A + row * rs + j * cs (complex
-// elements); B holds NT tiles of 16 pairs (row stride 16 NT), and every A
+// elements); B holds NT tiles of 16 pairs (row stride 16 NT + 1), and every A
 // element loaded feeds NT matrix-core products.  The inner index is split
 // into the same four interleaved partial sums for every NT, so a pair's
 // result does not depend on NT bit for bit.
@@ -667,7 +667,7 @@ __device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ 
                                           int64_t cs, const R *__restrict__ B, int wv, int lane, Store store)
 {
     typedef typename Mf<R>::V V;
-    constexpr int PW = 16 * NT, U = 4;
+    constexpr int PW = 16 * NT + 1, U = 4;  // B row stride, padded against LDS bank conflicts
     const int i16 = lane & 15, k4 = lane >> 4;
     const int n_rt = (2 * nrow + 15) >> 4, kmax = 2 * ncol;
     for (int rt = wv; rt < n_rt; rt += M2LC_WAVES) {
@@ -733,10 +733,10 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
                                                                  typename Cx<R>::T *__restrict__ part)
 {
     using C = typename Cx<R>::T;
-    constexpr int PW = 16 * NT;
+    constexpr int PW = 16 * NT, PS = PW + 1;  // pairs per chunk, padded LDS row stride
     extern __shared__ unsigned char shraw[];
-    R *XB = (R *)shraw;                        // [2 cols][PW]
-    R *TB = XB + (size_t)2 * cols * PW;        // [2 rmax][PW]
+    R *XB = (R *)shraw;                        // [2 cols][PS]
+    R *TB = XB + (size_t)2 * cols * PS;        // [2 rmax][PS]
     // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so XCD
     // x takes the contiguous chunk range [x per, (x + 1) per); chunks of one
     // operator are adjacent and reuse that XCD's L2
@@ -748,8 +748,8 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
     for (int e = tid; e < PW * cols; e += 64 * M2LC_WAVES) {
         const int p = e / cols, j = e - p * cols;
         const C v = p < n ? in[pr_src[p0 + p] + j] : Cx<R>::mk(0, 0);
-        XB[(2 * j) * PW + p] = v.x;
-        XB[(2 * j + 1) * PW + p] = v.y;
+        XB[(2 * j) * PS + p] = v.x;
+        XB[(2 * j + 1) * PS + p] = v.y;
     }
     __syncthreads();
     const C *M = mat + ch_mat[c];
@@ -767,7 +767,7 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
     } else {
         // T = V X (V: r x cols at M + s r, column-major), then Y = U T (U: s x r)
         auto to_t = [&](int row, int ci, int p, R v) {
-            if (row < r) TB[(2 * row + ci) * PW + p] = v;
+            if (row < r) TB[(2 * row + ci) * PS + p] = v;
         };
         mfma_rows<R, NT>(M + (size_t)s * r, r, cols, 1, (int64_t)r, XB, wv, lane, to_t);
         __syncthreads();
@@ -904,7 +904,7 @@ static int64_t slab_entries(const GemvList &G)
     return std::max<int64_t>(1, ((int64_t)1 << 30) / (16 * std::max(1, G.rows)));
 }
 
-static size_t mfma_shm(const DChunks &c) { return sizeof(double) * 2 * c.pw * (size_t)(c.cols + c.rmax); }
+static size_t mfma_shm(const DChunks &c) { return sizeof(double) * 2 * (c.pw + 1) * (size_t)(c.cols + c.rmax); }
 
 static DChunks upload_chunks(Device &D, const M2LChunks &C)
 {
