@@ -54,11 +54,45 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
 // complex type and elementary functions for the working precision R
+// sin and cos of kr for 0 <= x <~ 1e5: x = q pi/2 + t with q = rint(2x/pi),
+// t from two fused multiply-adds against pi/2 split into its nearest double
+// and the remainder (absolute error ~1e-16 for q < 2^20), then Taylor series
+// of sin and cos on |t| <= pi/4 through t^15 and t^16 (truncation below
+// 5e-17) and the quadrant of q.
+__device__ __forceinline__ void sincos_kr(double x, double *s, double *c)
+{
+    const double q = rint(x * 0.63661977236758134308);   // 2/pi
+    double t = fma(-q, 1.5707963267948966, x);             // pi/2 rounded to double
+    t = fma(-q, 6.123233995736766e-17, t);                 // pi/2 minus that double
+    const double t2 = t * t;
+    double ps = -1.0 / 1307674368000.0;                    // -1/15!
+    ps = fma(ps, t2, 1.0 / 6227020800.0);                  // 1/13!
+    ps = fma(ps, t2, -1.0 / 39916800.0);                   // -1/11!
+    ps = fma(ps, t2, 1.0 / 362880.0);                      // 1/9!
+    ps = fma(ps, t2, -1.0 / 5040.0);                       // -1/7!
+    ps = fma(ps, t2, 1.0 / 120.0);                         // 1/5!
+    ps = fma(ps, t2, -1.0 / 6.0);                          // -1/3!
+    const double sn = fma(ps * t2, t, t);
+    double pc = 1.0 / 20922789888000.0;                    // 1/16!
+    pc = fma(pc, t2, -1.0 / 87178291200.0);                // -1/14!
+    pc = fma(pc, t2, 1.0 / 479001600.0);                   // 1/12!
+    pc = fma(pc, t2, -1.0 / 3628800.0);                    // -1/10!
+    pc = fma(pc, t2, 1.0 / 40320.0);                       // 1/8!
+    pc = fma(pc, t2, -1.0 / 720.0);                        // -1/6!
+    pc = fma(pc, t2, 1.0 / 24.0);                          // 1/4!
+    pc = fma(pc, t2, -0.5);                                // -1/2!
+    const double cn = fma(pc, t2, 1.0);
+    const int n = ((int)(int64_t)q) & 3;
+    const double a = (n & 1) ? cn : sn, b = (n & 1) ? sn : cn;
+    *s = (n & 2) ? -a : a;
+    *c = ((n + 1) & 2) ? -b : b;
+}
+
 template <typename R> struct Cx;
 template <> struct Cx<double> {
     using T = double2;
     __device__ static T mk(double a, double b) { return make_double2(a, b); }
-    __device__ static void sc(double x, double *s, double *c) { sincos(x, s, c); }
+    __device__ static void sc(double x, double *s, double *c) { sincos_kr(x, s, c); }
     __device__ static double rs(double x) { return rsqrt(x); }
 };
 template <> struct Cx<float> {
