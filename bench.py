@@ -57,6 +57,36 @@ def m2l_work(plan_stats: dict) -> tuple[float, float]:
     return flops, byts
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bm_h_matvec_sphere_N4009008_k500.md")
+TRAFFIC_SOURCES = ("paper_1311_5202_amd/csrc/apply.hip", "paper_1311_5202_amd/csrc/templates.cpp",
+                   "paper_1311_5202_amd/csrc/tree.cpp")
+
+
+def source_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes of the M2L phase of one mat-vec from the committed counter
+    profile (FETCH_SIZE x 2 + WRITE_SIZE x 1, the copy-kernel factors), or None
+    when the profile is for another workload or the kernels changed since."""
+    if workload != "c5" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("<!-- traffic "):
+                rec = json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
+                if rec.get("source_sha256") == source_digest():
+                    return rec["m2l_hbm_bytes_per_matvec"]
+    return None
+
+
 def cpu_baseline(pts, nrm, w, u, k, n_rows: int):
     import numpy as np
 
@@ -280,14 +310,16 @@ def main() -> int:
     ms = 1e3 * dt / args.steps
     flops, byts = m2l_work(st)
     m2l_ms = phases["m2l"]
-    n_m2l_launch = max(1, sum(1 for L in st["levels"] if L["m2l_pairs"] > 0))
+    # kernel launches in the M2L phase: per slab one chunk kernel and one segmented sum
+    n_m2l_launch = max(1, 2 * sum(t[0] for t in st.get("m2l_tiles", []) if t[0] > 0)) if st.get("m2l_mode") == 3 \
+        else max(1, sum(1 for L in st["levels"] if L["m2l_pairs"] > 0))
     roof = {
         "bound": "mfma",
         "kernel": "M2L (all levels of one mat-vec)",
         "achieved": flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else 0.0,
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",
-        "traffic": None,
+        "traffic": measured_traffic(args.workload),
         "launches_per_matvec": n_m2l_launch,
         "algorithmic_flops_per_matvec": flops,
         "algorithmic_bytes_per_matvec": byts,

@@ -98,6 +98,7 @@ typedef struct {
                            conjugate coupling (see bm_solve). */
     int autotune;       /* 1 (default): at build, time 16 and 32 pairs per M2L chunk on the
                            plan's own lists and keep the faster per level; 0: 16 */
+    int slab_mb;        /* scratch for per-pair translation results, MiB per slab; 0 -> 1024 */
 } fda_opts;
 
 typedef struct fda_plan fda_plan;

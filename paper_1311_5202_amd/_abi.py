@@ -40,7 +40,8 @@ class FdaOpts(ctypes.Structure):
                 ("verbose", ctypes.c_int), ("wedge_factor", ctypes.c_int), ("m2l_tile", ctypes.c_int),
                 ("p2p_threshold", ctypes.c_double),
                 ("coupling", ctypes.c_double),
-                ("autotune", ctypes.c_int)]
+                ("autotune", ctypes.c_int),
+                ("slab_mb", ctypes.c_int)]
 
 
 class FdaError(RuntimeError):

@@ -84,6 +84,7 @@ int fda_default_opts(fda_opts *o)
     o->p2p_threshold = 0;
     o->coupling = 1.0;
     o->autotune = 1;
+    o->slab_mb = 0;
     return FDA_OK;
 }
 
@@ -141,6 +142,8 @@ int fda_build(const fda_geometry *g, double k, double eps, const fda_opts *o, fd
             if (!std::isfinite(o->coupling)) throw std::invalid_argument("non-finite coupling");
             opt.coupling = o->coupling != 0 ? o->coupling : 1.0;
             opt.autotune = o->autotune;
+            if (o->slab_mb < 0) throw std::invalid_argument("negative slab size");
+            if (o->slab_mb > 0) opt.slab_mb = o->slab_mb;
         }
         if (opt.precision < FDA_PREC_FP64 || opt.precision > FDA_PREC_BOTH) throw std::invalid_argument("unknown precision");
         if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");

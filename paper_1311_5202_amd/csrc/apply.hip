@@ -755,7 +755,7 @@ __device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ 
     }
 }
 
-template <typename R, bool TRANS, int NT>
+template <typename R, bool TRANS, int NT, int TAG>
 __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, int s, int cols, int rmax,
                                                                  const int64_t *__restrict__ ch_mat,
                                                                  const int *__restrict__ ch_rank,
@@ -812,7 +812,7 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
 // Sum of the per-pair results of each output slot (entries contiguous in
 // target-major order), one wavefront per output, lanes over rows; four
 // entries in flight per step, added in a fixed order.
-template <typename R>
+template <typename R, int TAG>
 __global__ __launch_bounds__(256) void k_seg_sum(int n_out, int s, const int64_t *__restrict__ red_out,
                                                  const int64_t *__restrict__ red_ptr,
                                                  const typename Cx<R>::T *__restrict__ part,
@@ -932,10 +932,10 @@ static DTiles upload_tiles(Device &D, const M2LTiles &T)
     return d;
 }
 
-// pairs per slab: the scratch of per-pair results stays near 1 GiB
-static int64_t slab_entries(const GemvList &G)
+// pairs per slab: the scratch of per-pair results stays within slab_mb MiB
+static int64_t slab_entries(const GemvList &G, int slab_mb)
 {
-    return std::max<int64_t>(1, ((int64_t)1 << 30) / (16 * std::max(1, G.rows)));
+    return std::max<int64_t>(1, ((int64_t)slab_mb << 20) / (16 * std::max(1, G.rows)));
 }
 
 static size_t mfma_shm(const DChunks &c) { return sizeof(double) * 2 * (c.pw + 1) * (size_t)(c.cols + c.rmax); }
@@ -1043,7 +1043,7 @@ static void autotune_m2l(Plan &P, Device &D)
         if (D.m2ls[l].empty()) continue;
         const GemvList &G = P.m2l_lists[l];
         std::vector<DChunks> alt;
-        for (const M2LChunks &C : build_chunk_slabs(G, 2 * M2LC_CH, slab_entries(G))) alt.push_back(upload_chunks(D, C));
+        for (const M2LChunks &C : build_chunk_slabs(G, 2 * M2LC_CH, slab_entries(G, P.opt.slab_mb))) alt.push_back(upload_chunks(D, C));
         const double t16 = time(D.m2ls[l]), t32 = time(alt);
         const bool take = t32 < t16;
         if (take) std::swap(D.m2ls[l], alt);
@@ -1132,7 +1132,7 @@ void device_upload(Plan &P)
             size_t part = 0, big = 0;
             auto slabs = [&](const GemvList &G, std::vector<DChunks> &dst) {
                 if (G.out_off.empty()) return;
-                for (const M2LChunks &C : build_chunk_slabs(G, M2LC_CH, slab_entries(G))) {
+                for (const M2LChunks &C : build_chunk_slabs(G, M2LC_CH, slab_entries(G, P.opt.slab_mb))) {
                     dst.push_back(upload_chunks(D, C));
                     part = std::max(part, sizeof(double2) * (size_t)C.pr_pos.size() * (size_t)C.s);
                     big = std::max(big, dst.back().shm / 2);  // FP32 VALU kernel (FP64 runs on MFMA)
@@ -1154,10 +1154,18 @@ void device_upload(Plan &P)
             if (mf > (size_t)maxsh) throw std::runtime_error("translation operator too large for LDS");
             if (mf > 65536)
                 for (const void *f :
-                     {(const void *)k_chunks_mfma<double, false, 1>, (const void *)k_chunks_mfma<double, true, 1>,
-                      (const void *)k_chunks_mfma<float, false, 1>, (const void *)k_chunks_mfma<float, true, 1>,
-                      (const void *)k_chunks_mfma<double, false, 2>, (const void *)k_chunks_mfma<double, true, 2>,
-                      (const void *)k_chunks_mfma<float, false, 2>, (const void *)k_chunks_mfma<float, true, 2>})
+                     {(const void *)k_chunks_mfma<double, false, 1, TAG_M2L>,
+                      (const void *)k_chunks_mfma<double, false, 1, TAG_M2M>,
+                      (const void *)k_chunks_mfma<double, true, 1, TAG_L2L>,
+                      (const void *)k_chunks_mfma<float, false, 1, TAG_M2L>,
+                      (const void *)k_chunks_mfma<float, false, 1, TAG_M2M>,
+                      (const void *)k_chunks_mfma<float, true, 1, TAG_L2L>,
+                      (const void *)k_chunks_mfma<double, false, 2, TAG_M2L>,
+                      (const void *)k_chunks_mfma<double, false, 2, TAG_M2M>,
+                      (const void *)k_chunks_mfma<double, true, 2, TAG_L2L>,
+                      (const void *)k_chunks_mfma<float, false, 2, TAG_M2L>,
+                      (const void *)k_chunks_mfma<float, false, 2, TAG_M2M>,
+                      (const void *)k_chunks_mfma<float, true, 2, TAG_L2L>})
                     HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mf));
             D.part_bytes = part;
             if (part) D.part = dalloc<double2>(D, part / sizeof(double2));
@@ -1370,12 +1378,12 @@ static void launch_slabs(const std::vector<DChunks> &S, void *part, const typena
         const size_t shm = mfma_shm(c) * sizeof(R) / sizeof(double);
         const unsigned grid = (unsigned)(((c.n + kXcds - 1) / kXcds) * kXcds);
         if (c.pw == 32)
-            hipLaunchKernelGGL((k_chunks_mfma<R, TRANS, 2>), dim3(grid), dim3(64 * M2LC_WAVES), shm, st, c.n, c.s,
+            hipLaunchKernelGGL((k_chunks_mfma<R, TRANS, 2, TAG>), dim3(grid), dim3(64 * M2LC_WAVES), shm, st, c.n, c.s,
                                c.cols, c.rmax, c.ch_mat, c.ch_rank, c.ch_pptr, c.pr_src, c.pr_pos, mat, in, (C *)part);
         else
-            hipLaunchKernelGGL((k_chunks_mfma<R, TRANS, 1>), dim3(grid), dim3(64 * M2LC_WAVES), shm, st, c.n, c.s,
+            hipLaunchKernelGGL((k_chunks_mfma<R, TRANS, 1, TAG>), dim3(grid), dim3(64 * M2LC_WAVES), shm, st, c.n, c.s,
                                c.cols, c.rmax, c.ch_mat, c.ch_rank, c.ch_pptr, c.pr_src, c.pr_pos, mat, in, (C *)part);
-        hipLaunchKernelGGL((k_seg_sum<R>), dim3((c.n_out + 3) / 4), dim3(256), 0, st, c.n_out, c.s, c.red_out,
+        hipLaunchKernelGGL((k_seg_sum<R, TAG>), dim3((c.n_out + 3) / 4), dim3(256), 0, st, c.n_out, c.s, c.red_out,
                            c.red_ptr, (const C *)part, out);
     }
 }
