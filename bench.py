@@ -32,6 +32,11 @@ sys.path.insert(0, ROOT)
 # kD ~ U[5, 60], FP32 far and near field, all instances in one graph launch
 BATCH = {"c3": (64, 2, (10_000, 100_000), (5.0, 60.0))}
 
+# learned-preconditioner evaluation: star/ellipsoid training surfaces at
+# kD ~ U[20, 80], held-out surfaces at kD = 50, FP32 GMRES to 1e-4
+LEARNED = {"c4": {"train": 16, "held_out": 8, "n_split": 16, "kd_train": (20.0, 80.0), "kd_test": 50.0,
+                  "seed_train": 3, "seed_test": 4}}
+
 WORKLOADS = {
     # name: (octahedral split n, k, eps, description)
     "c1": (8, 5.0, 1e-4, "unit sphere, 512 quadratic triangles, N=3072, k=5 (kD=10), eps=1e-4"),
@@ -41,6 +46,7 @@ WORKLOADS = {
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
+P2P_FLOPS_PER_PAIR = 67
 
 
 def m2l_work(plan_stats: dict) -> tuple[float, float]:
@@ -87,7 +93,10 @@ def measured_traffic(workload: str):
     return None
 
 
-def cpu_baseline(pts, nrm, w, u, k, n_rows: int):
+def cpu_baseline(pts, nrm, w, u, k, n_rows: int, gpu_rows=None):
+    """The oracle's dense FP64 H sum timed on a seeded sample of target rows
+    and scaled to a full mat-vec.  gpu_rows: {name: full GPU result of the
+    same raw H sum}; their relative L2 error on the sample is reported."""
     import numpy as np
 
     import oracle
@@ -95,11 +104,14 @@ def cpu_baseline(pts, nrm, w, u, k, n_rows: int):
     rows = np.sort(np.random.default_rng(7).choice(len(w), n_rows, replace=False))
     oracle.dense_rows(pts[:64], nrm[:64], w[:64], u[:64], k, "H", rows=np.arange(4))  # load + warm
     t0 = time.perf_counter()
-    oracle.dense_rows(pts, nrm, w, u, k, "H", rows=rows)
+    ref = oracle.dense_rows(pts, nrm, w, u, k, "H", rows=rows)
     dt = time.perf_counter() - t0
     full = dt * len(w) / n_rows
-    return {"value": 1.0 / full, "unit": "matvec/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"dense FP64 H sum on {n_rows} of {len(w)} target rows ({dt:.1f} s), scaled to a full mat-vec"}
+    out = {"value": 1.0 / full, "unit": "matvec/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"dense FP64 H sum on {n_rows} of {len(w)} target rows ({dt:.1f} s), scaled to a full mat-vec"}
+    for name, g in (gpu_rows or {}).items():
+        out[f"gpu_{name}_rel_l2_on_sample"] = oracle.rel_l2(g[rows], ref)
+    return out
 
 
 def train_learned(fdb, synth, density: float, coupling: float, epochs: int, log):
@@ -163,6 +175,97 @@ def gmres_compare(fdb, synth, plan, tol: float, coupling: float, epochs: int, lo
     net.close()
     out["speedup_fp32_learned_vs_fp64_plain"] = out["fp64_plain"]["seconds"] / out["fp32_learned"]["seconds"]
     return out
+
+
+def learned_main(args, fdb, synth, torch) -> int:
+    """Train the coupling network on seeded training surfaces, then compare
+    FP32 GMRES to 1e-4 with block-Jacobi alone and with the learned coupling
+    on held-out surfaces (plane waves from seeded random directions)."""
+    import numpy as np
+
+    cfg = LEARNED[args.workload]
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+
+    def surfaces(count, seed, kd_range):
+        rng = np.random.default_rng(seed)
+        out = []
+        for _ in range(count):
+            if rng.uniform() < 0.5:
+                el = synth.star_surface(cfg["n_split"], int(rng.integers(0, 2**31 - 1)))
+            else:
+                el = synth.ellipsoid(cfg["n_split"], float(rng.uniform(1.0, 4.0)))
+            p = el.reshape(-1, 3)
+            D = float(np.max(p.max(0) - p.min(0)))
+            out.append((el, float(rng.uniform(*kd_range)) / D))
+        return out
+
+    def build(el, k):
+        pts, nrm, w = fdb.nystrom_nodes(el)
+        return fdb.build(pts, nrm, w, k, 1e-4, elements=el, corrections=1, precision="both", coupling=args.coupling)
+
+    t0 = time.perf_counter()
+    train = [build(el, k) for el, k in surfaces(cfg["train"], cfg["seed_train"], cfg["kd_train"])]
+    t_build = time.perf_counter() - t0
+    net = fdb.Net(17)
+    first = sum(net.loss_grad(p)[0] for p in train)
+    t0 = time.perf_counter()
+    for ep in range(args.epochs):
+        last = sum(net.train_step(p, 3e-3) for p in train)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"[bench] trained on {len(train)} surfaces: loss {first:.1f} -> {last:.1f} in {t_train:.1f} s")
+    for p in train:
+        p.close()
+    dirs = synth.random_directions(cfg["held_out"], cfg["seed_test"] + 100)
+    rows = []
+    for i, (el, k) in enumerate(surfaces(cfg["held_out"], cfg["seed_test"], (cfg["kd_test"], cfg["kd_test"]))):
+        plan = build(el, k)
+        rhs = plan.rhs_plane_wave(dirs[i])
+        plan.solve(rhs, 1e-4, maxit=300, restart=300, precond=1, fp32=True, raise_on_fail=False)  # set-up
+        net.attach(plan)
+        res = {}
+        for name, pc in (("block_jacobi", 1), ("learned", 2)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = plan.solve(rhs, 1e-4, maxit=300, restart=300, precond=pc, fp32=True, raise_on_fail=False)
+            torch.cuda.synchronize()
+            res[name] = (info["iterations"], time.perf_counter() - t1, info["status"])
+        log(f"[bench] held-out {i}: N={plan.n} k={k:.1f} block-Jacobi {res['block_jacobi'][:2]}, "
+            f"learned {res['learned'][:2]}")
+        rows.append(res)
+        plan.close()
+    it_bj = float(np.mean([r["block_jacobi"][0] for r in rows]))
+    it_ln = float(np.mean([r["learned"][0] for r in rows]))
+    t_bj = float(np.mean([r["block_jacobi"][1] for r in rows]))
+    t_ln = float(np.mean([r["learned"][1] for r in rows]))
+    out = {
+        "metric": "held-out GMRES time to 1e-4, FP32 FDA, block-Jacobi + learned coupling",
+        "value": t_ln,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": len(rows),
+        "warmup": 1,
+        "ms_per_step": 1e3 * t_ln,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg['train']} training surfaces (star/ellipsoid, N={48 * cfg['n_split'] ** 2}, "
+                               f"kD~U{list(cfg['kd_train'])}), {cfg['held_out']} held out at kD={cfg['kd_test']}",
+                   "alpha": f"{args.coupling:g}i/k", "parallelism": "single GPU"},
+        "iterations_block_jacobi": it_bj,
+        "iterations_learned": it_ln,
+        "seconds_block_jacobi": t_bj,
+        "iteration_reduction": 1.0 - it_ln / it_bj,
+        "converged": all(r[n][2] == 0 for r in rows for n in r),
+        "train_s": t_train,
+        "build_train_s": t_build,
+        "roofline": None,
+    }
+    net.close()
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def batch_main(args, fdb, synth, torch) -> int:
@@ -237,7 +340,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=os.environ.get("FDBEM_WORKLOAD", "c5"),
-                    choices=sorted(WORKLOADS) + sorted(BATCH))
+                    choices=sorted(WORKLOADS) + sorted(BATCH) + sorted(LEARNED))
     ap.add_argument("--instances", type=int, default=0, help="batched workload: number of instances (0: 64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0)
@@ -266,6 +369,8 @@ def main() -> int:
         del src, dst
     if args.workload in BATCH:
         return batch_main(args, fdb, synth, torch)
+    if args.workload in LEARNED:
+        return learned_main(args, fdb, synth, torch)
     n_split, k, eps, desc = WORKLOADS[args.workload]
     el = synth.octa_sphere(n_split)
     pts, nrm, w = fdb.nystrom_nodes(el)
@@ -308,6 +413,8 @@ def main() -> int:
             "rel_l2_vs_fp64": (torch.linalg.norm(out32 - out) / torch.linalg.norm(out)).item()}
     print(f"[bench] FP32 mat-vec {fp32}", file=sys.stderr, flush=True)
     ms = 1e3 * dt / args.steps
+    free, total = torch.cuda.mem_get_info()
+    peak_used = total - free
     flops, byts = m2l_work(st)
     m2l_ms = phases["m2l"]
     # kernel launches in the M2L phase: per slab one chunk kernel and one segmented sum
@@ -325,6 +432,14 @@ def main() -> int:
         "algorithmic_bytes_per_matvec": byts,
     }
     roof["frac"] = roof["achieved"] / roof["peak"]
+    # P2P against the FP64 vector peak: 67 flops per pair for the H kernel
+    # (distance, rsqrt, sin and cos each counted once, kernel and accumulation)
+    p2p_flops = P2P_FLOPS_PER_PAIR * st["p2p_pairs"]
+    p2p_roof = {"bound": "valu", "kernel": "P2P (near-field point sums)",
+                "achieved": p2p_flops / (phases["p2p"] * 1e-3) / 1e12 if phases["p2p"] > 0 else 0.0,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "flops_per_pair": P2P_FLOPS_PER_PAIR,
+                "pairs": st["p2p_pairs"]}
+    p2p_roof["frac"] = p2p_roof["achieved"] / p2p_roof["peak"]
     res = {
         "metric": "FDA matvecs/s (Burton-Miller H operator)",
         "value": args.steps / dt,
@@ -343,14 +458,21 @@ def main() -> int:
         "phase_ms": phases,
         "build_s": t_build,
         "roofline": roof,
+        "p2p_roofline": p2p_roof,
         "fp32": fp32,
     }
     if not args.no_solve and op == "BM_H":
         log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
         res["gmres"] = gmres_compare(fdb, synth, plan, 1e-4, args.coupling, args.epochs, log)
+    free, total = torch.cuda.mem_get_info()
+    res["peak_device_gb"] = max(peak_used, total - free) / 1e9
+    res["plan_device_gb"] = plan.stats().get("device_bytes", 0) / 1e9
     if not args.no_cpu_baseline:
         n_rows = args.cpu_rows or max(64, min(N, int(2.5e9 / N)))
-        res["cpu_baseline"] = cpu_baseline(pts, nrm, w, u_host, k, n_rows)
+        # the same raw H sum on the GPU (FP64 and FP32) for parity on the oracle's sample
+        raw = {"raw_h_fp64": plan.matvec(u, "RAW_H").cpu().numpy(),
+               "raw_h_fp32": plan.matvec(u, "RAW_H", fp32=True).cpu().numpy()}
+        res["cpu_baseline"] = cpu_baseline(pts, nrm, w, u_host, k, n_rows, raw)
     plan.close()
     print(json.dumps(res), flush=True)
     return 0
