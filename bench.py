@@ -93,7 +93,7 @@ def measured_traffic(workload: str):
     return None
 
 
-def cpu_baseline(pts, nrm, w, u, k, n_rows: int, gpu_rows=None):
+def cpu_baseline(pts, nrm, w, u, k, n_rows: int, gpu_rows=None, coupling: float = 1.0):
     """The oracle's dense FP64 H sum timed on a seeded sample of target rows
     and scaled to a full mat-vec.  gpu_rows: {name: full GPU result of the
     same raw H sum}; their relative L2 error on the sample is reported."""
@@ -104,7 +104,8 @@ def cpu_baseline(pts, nrm, w, u, k, n_rows: int, gpu_rows=None):
     rows = np.sort(np.random.default_rng(7).choice(len(w), n_rows, replace=False))
     oracle.dense_rows(pts[:64], nrm[:64], w[:64], u[:64], k, "H", rows=np.arange(4))  # load + warm
     t0 = time.perf_counter()
-    ref = oracle.dense_rows(pts, nrm, w, u, k, "H", rows=rows)
+    # the H kernel with alpha = i coupling / k, as the plan
+    ref = oracle.dense_rows(pts, nrm, w, u, k, "H", rows=rows, coefs=(0.0, 1.0, 1.0, 1j * coupling / k))
     dt = time.perf_counter() - t0
     full = dt * len(w) / n_rows
     out = {"value": 1.0 / full, "unit": "matvec/s", "cores": oracle.num_threads(), "kind": "oracle",
@@ -472,7 +473,7 @@ def main() -> int:
         # the same raw H sum on the GPU (FP64 and FP32) for parity on the oracle's sample
         raw = {"raw_h_fp64": plan.matvec(u, "RAW_H").cpu().numpy(),
                "raw_h_fp32": plan.matvec(u, "RAW_H", fp32=True).cpu().numpy()}
-        res["cpu_baseline"] = cpu_baseline(pts, nrm, w, u_host, k, n_rows, raw)
+        res["cpu_baseline"] = cpu_baseline(pts, nrm, w, u_host, k, n_rows, raw, args.coupling)
     plan.close()
     print(json.dumps(res), flush=True)
     return 0
