@@ -78,3 +78,38 @@ def test_nystrom_nodes_match_oracle():
         assert np.max(np.abs(p - p2)) < 1e-14
         assert np.max(np.abs(n - n2)) < 1e-13
         assert np.max(np.abs(w - w2)) < 1e-15 * 10
+
+
+def test_launch_and_learned_entry_points_reject_null_arguments():
+    """Batch, graph and learned-network entry points validate their
+    arguments before any device work."""
+    L = fdb.lib()
+    out = ctypes.c_void_p()
+    assert L.fda_set_graph(None, 1) == _abi.FDA_EINVAL
+    assert L.fda_batch_create(None, 0, ctypes.byref(out)) == _abi.FDA_EINVAL
+    assert L.fda_batch_create(None, 3, ctypes.byref(out)) == _abi.FDA_EINVAL
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.fda_batch_create(arr, 2, ctypes.byref(out)) == _abi.FDA_EINVAL
+    assert L.fda_batch_matvec(None, 3, None, None, None) == _abi.FDA_EINVAL
+    assert L.fda_batch_solve(None, 3, None, 1e-4, 10, 10, 0, None, None, None, None) == _abi.FDA_EINVAL
+    L.fda_batch_destroy(None)
+    assert L.fda_net_num_params() == 12 * 32 + 32 + 32 * 16 + 16
+    assert L.fda_net_create(0, None) == _abi.FDA_EINVAL
+    assert L.fda_net_get_params(None, None) == _abi.FDA_EINVAL
+    assert L.fda_net_set_params(None, None) == _abi.FDA_EINVAL
+    loss = ctypes.c_double()
+    assert L.fda_net_loss_grad(None, None, ctypes.byref(loss), None) == _abi.FDA_EINVAL
+    assert L.fda_net_train_step(None, None, 1e-3, None) == _abi.FDA_EINVAL
+    assert L.fda_net_attach(None, None) == _abi.FDA_EINVAL
+    assert L.fda_net_loss_grad_raw(None, 0, None, None, None, None, None, 0, None, None, None,
+                                   ctypes.byref(loss), None) == _abi.FDA_EINVAL
+    L.fda_net_destroy(None)
+    assert "null" in L.fda_last_error().decode() or L.fda_last_error()
+
+
+def test_option_validation():
+    pts, nrm, w = _geom(10)
+    for bad in ({"coupling": float("nan")}, {"slab_mb": -1}):
+        with pytest.raises(_abi.FdaError) as e:
+            fdb.build(pts, nrm, w, 5.0, 1e-4, **bad)
+        assert e.value.code == _abi.FDA_EINVAL
