@@ -254,13 +254,12 @@ __global__ __launch_bounds__(256) void k_p2p(int n_leaf, const int64_t *__restri
     const int64_t t0 = ts[leaf], t1 = te[leaf];
     const int e0 = ptr[leaf], e1 = ptr[leaf + 1];
     for (int64_t ib = t0; ib < t1; ib += 64) {
+        // lane = t + nt q: target t, source slice q of S = 64 / nt
         const int nt = (int)min((int64_t)64, t1 - ib);
-        int ntp = 1;
-        while (ntp < nt) ntp <<= 1;
-        const int S = 64 / ntp;
-        const int t = lane & (ntp - 1), q = lane / ntp;
-        const bool act = t < nt;
-        const int64_t i = ib + (act ? t : 0);
+        const int S = 64 / nt;
+        const int q = lane / nt, t = lane - q * nt;
+        const bool act = q < S;
+        const int64_t i = ib + t;
         const PN X = pn[i];
         C acc = Cx<R>::mk(0, 0);
         if (act) {
@@ -276,11 +275,15 @@ __global__ __launch_bounds__(256) void k_p2p(int n_leaf, const int64_t *__restri
                 }
             }
         }
-        for (int off = ntp; off < 64; off <<= 1) {
-            acc.x += __shfl_xor(acc.x, off);
-            acc.y += __shfl_xor(acc.y, off);
+        // slices added in order q = 0, 1, .., S - 1 into the lanes of slice 0
+        C sum = acc;
+        for (int j = 1; j < S; ++j) {
+            const int src = min(t + j * nt, 63);
+            const R vx = __shfl(acc.x, src), vy = __shfl(acc.y, src);
+            sum.x += vx;
+            sum.y += vy;
         }
-        if (act && q == 0) res[ib + t] = to64(acc);
+        if (q == 0) res[ib + t] = to64(sum);
     }
 }
 
@@ -696,15 +699,16 @@ struct Mf<float> {
 // element loaded feeds NT matrix-core products.  The inner index is split
 // into the same four interleaved partial sums for every NT, so a pair's
 // result does not depend on NT bit for bit.
+// One 16-row tile rt over the real inner range [kb, ke) (kb a multiple of 4).
 template <typename R, int NT, typename Store>
-__device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ A, int nrow, int ncol, int64_t rs,
-                                          int64_t cs, const R *__restrict__ B, int wv, int lane, Store store)
+__device__ __forceinline__ void mfma_tile(const typename Cx<R>::T *__restrict__ A, int nrow, int64_t rs, int64_t cs,
+                                          const R *__restrict__ B, int rt, int kb, int ke, int lane, Store store)
 {
     typedef typename Mf<R>::V V;
     constexpr int PW = 16 * NT + 1, U = 4;  // B row stride, padded against LDS bank conflicts
     const int i16 = lane & 15, k4 = lane >> 4;
-    const int n_rt = (2 * nrow + 15) >> 4, kmax = 2 * ncol;
-    for (int rt = wv; rt < n_rt; rt += M2LC_WAVES) {
+    const int kmax = ke;
+    {
         const int I = rt * 16 + i16, row = I >> 1, ci = I & 1;
         const bool rok = row < nrow;
         const R *arow = (const R *)(A + (rok ? row : 0) * rs);
@@ -717,12 +721,16 @@ __device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ 
         const int d = k4 & 1;
         const R sgn = (ci == 0 && d == 1) ? (R)-1 : (R)1;
         const int sel = ci ^ d;
-        int k0 = 0;
+        int k0 = kb;
         for (; k0 + 4 * U <= kmax; k0 += 4 * U) {
             const int j0 = (k0 + k4) >> 1;
             R x[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) x[u] = rok ? arow[2 * (j0 + 2 * u) * cs + sel] : (R)0;
+            for (int u = 0; u < U; ++u) {
+                // always load (arow is row 0 for rows past the end), then mask: no branches
+                const R xv = arow[2 * (j0 + 2 * u) * cs + sel];
+                x[u] = rok ? xv : (R)0;
+            }
             const R *bp = B + (k0 + k4) * PW + i16;
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -730,16 +738,15 @@ __device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ 
                 for (int t = 0; t < NT; ++t) acc[u][t] = Mf<R>::mma(sgn * x[u], bp[4 * u * PW + 16 * t], acc[u][t]);
         }
         for (; k0 < kmax; k0 += 4) {
-            const int K = k0 + k4, jj = K >> 1, dd = K & 1;
-            R a = 0;
-            if (K < kmax) {
-                const R x = rok ? arow[2 * jj * cs + (ci ^ dd)] : (R)0;
-                a = (ci == 0 && dd == 1) ? -x : x;
-            }
+            const int K = k0 + k4, Kc = min(K, kmax - 1), jj = Kc >> 1, dd = Kc & 1;
+            const bool kok = K < kmax;
+            const R xv = arow[2 * jj * cs + (ci ^ dd)];
+            const R x = (rok && kok) ? xv : (R)0;
+            const R a = (ci == 0 && dd == 1) ? -x : x;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const R b = K < kmax ? B[K * PW + 16 * t + i16] : (R)0;
-                acc[0][t] = Mf<R>::mma(a, b, acc[0][t]);
+                const R bv = B[Kc * PW + 16 * t + i16];
+                acc[0][t] = Mf<R>::mma(a, kok ? bv : (R)0, acc[0][t]);
             }
         }
 #pragma unroll
@@ -750,10 +757,34 @@ __device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ 
 #pragma unroll
                 for (int u = 0; u < U; ++u) v += acc[u][t][q];
                 const int Io = rt * 16 + Mf<R>::out_row(q, k4);
-                store(Io >> 1, Io & 1, 16 * t + i16, v);
+                store(Io >> 1, Io & 1, t, 16 * t + i16, v);
             }
     }
 }
+
+// All row tiles over the full inner range, dealt to the wavefronts.
+template <typename R, int NT, typename Store>
+__device__ __forceinline__ void mfma_rows(const typename Cx<R>::T *__restrict__ A, int nrow, int ncol, int64_t rs,
+                                          int64_t cs, const R *__restrict__ B, int wv, int lane, Store store)
+{
+    const int n_rt = (2 * nrow + 15) >> 4;
+    for (int rt = wv; rt < n_rt; rt += M2LC_WAVES) mfma_tile<R, NT>(A, nrow, rs, cs, B, rt, 0, 2 * ncol, lane, store);
+}
+
+// Split of the first low-rank product T = V X over the wavefronts: with
+// n_rt < 4 row tiles of T, the inner range 2 cols is cut into ns slices of
+// kstep (a multiple of 16) so every wavefront has a (tile, slice) unit; the
+// slices are added afterwards in a fixed order.
+struct KSplit {
+    int n_rt, ns, kstep;
+    __device__ KSplit(int r, int cols)
+    {
+        n_rt = (2 * r + 15) >> 4;
+        const int want = n_rt < M2LC_WAVES ? M2LC_WAVES / n_rt : 1, kmax = 2 * cols;
+        kstep = (((kmax + want - 1) / want) + 15) & ~15;
+        ns = want > 1 ? (kmax + kstep - 1) / kstep : 1;
+    }
+};
 
 template <typename R, bool TRANS, int NT, int TAG>
 __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, int s, int cols, int rmax,
@@ -779,18 +810,32 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
     if (c >= n_chunks) return;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int p0 = ch_pptr[c], n = ch_pptr[c + 1] - p0;
-    for (int e = tid; e < PW * cols; e += 64 * M2LC_WAVES) {
-        const int p = e / cols, j = e - p * cols;
-        const C v = p < n ? in[pr_src[p0 + p] + j] : Cx<R>::mk(0, 0);
-        XB[(2 * j) * PS + p] = v.x;
-        XB[(2 * j + 1) * PS + p] = v.y;
+    {
+        // tpp threads per pair, each reading every tpp-th element of its pair's source vector
+        constexpr int tpp = 64 * M2LC_WAVES / PW;
+        const int p = tid / tpp, sub = tid - p * tpp;
+        const bool pok = p < n;
+        const C *src = in + (pok ? pr_src[p0 + p] : 0);
+#pragma unroll 4
+        for (int j = sub; j < cols; j += tpp) {
+            const C v = src[j];
+            XB[(2 * j) * PS + p] = pok ? v.x : (R)0;
+            XB[(2 * j + 1) * PS + p] = pok ? v.y : (R)0;
+        }
+    }
+    // scratch row of each of this lane's pairs (lane & 15 + 16 t), -1 past the chunk's end
+    int64_t pos[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int p = 16 * t + (lane & 15);
+        pos[t] = p < n ? pr_pos[p0 + p] : -1;
     }
     __syncthreads();
     const C *M = mat + ch_mat[c];
     const int r = ch_rank[c];
     R *P = (R *)part;
-    auto to_part = [&](int row, int ci, int p, R v) {
-        if (row < s && p < n) P[2 * (pr_pos[p0 + p] * s + row) + ci] = v;
+    auto to_part = [&](int row, int ci, int t, int, R v) {
+        if (row < s && pos[t] >= 0) P[2 * (pos[t] * s + row) + ci] = v;
     };
     if (r < 0) {
         // dense s x cols, column-major (or its transpose stored cols x s)
@@ -800,11 +845,33 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
             mfma_rows<R, NT>(M, s, cols, 1, (int64_t)s, XB, wv, lane, to_part);
     } else {
         // T = V X (V: r x cols at M + s r, column-major), then Y = U T (U: s x r)
-        auto to_t = [&](int row, int ci, int p, R v) {
-            if (row < r) TB[(2 * row + ci) * PS + p] = v;
-        };
-        mfma_rows<R, NT>(M + (size_t)s * r, r, cols, 1, (int64_t)r, XB, wv, lane, to_t);
-        __syncthreads();
+        const KSplit ks(r, cols);
+        if (ks.ns == 1) {
+            auto to_t = [&](int row, int ci, int, int p, R v) {
+                if (row < r) TB[(2 * row + ci) * PS + p] = v;
+            };
+            mfma_rows<R, NT>(M + (size_t)s * r, r, cols, 1, (int64_t)r, XB, wv, lane, to_t);
+            __syncthreads();
+        } else {
+            // slice q of T goes to rows [16 n_rt q, 16 n_rt (q + 1)) of TB, then slice 0 += 1, 2, 3
+            const int q = wv / ks.n_rt, rt = wv - q * ks.n_rt, kb = q * ks.kstep;
+            R *slab = TB + (size_t)q * 16 * ks.n_rt * PS;
+            auto to_s = [&](int row, int ci, int, int p, R v) {
+                if (row < r) slab[(2 * row + ci) * PS + p] = v;
+            };
+            if (q < ks.ns)
+                mfma_tile<R, NT>(M + (size_t)s * r, r, 1, (int64_t)r, XB, rt, kb, min(2 * cols, kb + ks.kstep), lane,
+                                 to_s);
+            __syncthreads();
+            const int stride = 16 * ks.n_rt * PS;
+            for (int e = tid; e < 2 * r * PW; e += 64 * M2LC_WAVES) {
+                const int row = e / PW, p = e - row * PW;
+                R v = TB[row * PS + p];
+                for (int j = 1; j < ks.ns; ++j) v += TB[j * stride + row * PS + p];
+                TB[row * PS + p] = v;
+            }
+            __syncthreads();
+        }
         mfma_rows<R, NT>(M, s, r, 1, (int64_t)s, TB, wv, lane, to_part);
     }
 }
@@ -938,7 +1005,13 @@ static int64_t slab_entries(const GemvList &G, int slab_mb)
     return std::max<int64_t>(1, ((int64_t)slab_mb << 20) / (16 * std::max(1, G.rows)));
 }
 
-static size_t mfma_shm(const DChunks &c) { return sizeof(double) * 2 * (c.pw + 1) * (size_t)(c.cols + c.rmax); }
+// LDS of the chunk kernel: sources [2 cols][pw + 1] and T [tb rows][pw + 1];
+// low-rank chunks need at least 64 rows of T for the split first product
+static size_t mfma_shm(const DChunks &c)
+{
+    const size_t tb = (size_t)(c.lowrank ? std::max(2 * c.rmax, 64) : 2 * c.rmax);
+    return sizeof(double) * (c.pw + 1) * (2 * (size_t)c.cols + tb);
+}
 
 static DChunks upload_chunks(Device &D, const M2LChunks &C)
 {
@@ -947,6 +1020,7 @@ static DChunks upload_chunks(Device &D, const M2LChunks &C)
     d.s = C.s;
     d.cols = C.cols;
     d.rmax = std::max(1, C.max_rank);
+    d.lowrank = C.max_rank > 0;
     if (d.n == 0) return d;
     d.shm = sizeof(double2) * (size_t)M2LC_WAVES * (M2LC_CH * d.cols + M2LC_CH * d.rmax);
     d.ch_mat = dupload(D, C.ch_mat);

@@ -28,6 +28,7 @@ struct DTiles {
 
 struct DChunks {
     int n = 0, s = 0, cols = 0, rmax = 1;
+    bool lowrank = false;            // some chunk holds a low-rank (U, V) operator
     size_t shm = 0;
     int64_t *ch_mat = nullptr, *pr_tgt = nullptr, *pr_src = nullptr;
     int *ch_rank = nullptr, *ch_pptr = nullptr;
