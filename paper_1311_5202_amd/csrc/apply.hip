@@ -82,7 +82,7 @@ __device__ __forceinline__ void sincos_kr(double x, double *s, double *c)
     pc = fma(pc, t2, 1.0 / 24.0);                          // 1/4!
     pc = fma(pc, t2, -0.5);                                // -1/2!
     const double cn = fma(pc, t2, 1.0);
-    const int n = ((int)(int64_t)q) & 3;
+    const int n = ((int)q) & 3;                              // q < 2^31 for the kr of any plan
     const double a = (n & 1) ? cn : sn, b = (n & 1) ? sn : cn;
     *s = (n & 2) ? -a : a;
     *c = ((n + 1) & 2) ? -b : b;
@@ -265,14 +265,24 @@ __global__ __launch_bounds__(256) void k_p2p(int n_leaf, const int64_t *__restri
         if (act) {
             for (int e = e0; e < e1; ++e) {
                 const int64_t s1 = se[e];
-                for (int64_t j = ss[e] + q; j < s1; j += S) {
-                    if (j == i) continue;
-                    const PN Y = pn[j];
-                    // the difference in FP64 keeps the phase accurate; the kernel runs in R
-                    const C K = kernel_op<OPK, R>((R)(X.x - Y.x), (R)(X.y - Y.y), (R)(X.z - Y.z), (R)X.nx, (R)X.ny,
-                                                  (R)X.nz, (R)Y.nx, (R)Y.ny, (R)Y.nz, kr, ik);
-                    acc = cadd(acc, cmul(K, from64<C>(dens[j])));
+                // the difference in FP64 keeps the phase accurate; the kernel runs in R.
+                // The self pair (r = 0) is excluded by a select, not a branch.
+                auto term = [&](const PN &Y, int64_t j) {
+                    C K = kernel_op<OPK, R>((R)(X.x - Y.x), (R)(X.y - Y.y), (R)(X.z - Y.z), (R)X.nx, (R)X.ny,
+                                            (R)X.nz, (R)Y.nx, (R)Y.ny, (R)Y.nz, kr, ik);
+                    return j == i ? Cx<R>::mk(0, 0) : K;
+                };
+                int64_t j = ss[e] + q;
+                // two sources per step, both loaded before either kernel is evaluated;
+                // terms are added in source order
+                for (; j + S < s1; j += 2 * S) {
+                    const PN Y0 = pn[j], Y1 = pn[j + S];
+                    const C d0 = from64<C>(dens[j]), d1 = from64<C>(dens[j + S]);
+                    const C K0 = term(Y0, j), K1 = term(Y1, j + S);
+                    acc = cadd(acc, cmul(K0, d0));
+                    acc = cadd(acc, cmul(K1, d1));
                 }
+                if (j < s1) acc = cadd(acc, cmul(term(pn[j], j), from64<C>(dens[j])));
             }
         }
         // slices added in order q = 0, 1, .., S - 1 into the lanes of slice 0
@@ -287,93 +297,166 @@ __global__ __launch_bounds__(256) void k_p2p(int n_leaf, const int64_t *__restri
     }
 }
 
-// S2M: check potentials of the leaf's sources at the level's check points
-// (template + leaf centre), then x = W phi written to the outgoing slot.
 constexpr int LEAF_BLOCK = 256;
+constexpr int L2T_G = 8;  // leaves per workgroup in S2M and L2T
+// S2M: a workgroup takes up to L2T_G leaves of one template.  Check
+// potentials phi_g of every leaf's sources at the level's check points
+// (template + leaf centre; thread per (leaf, check point)), then x_g = W phi_g
+// added to each leaf's outgoing slot (thread per row of W, W read once per
+// group).
 template <typename R, typename O>
-__global__ __launch_bounds__(LEAF_BLOCK) void k_s2m(const int64_t *__restrict__ start, const int64_t *__restrict__ end,
-                                                    const int64_t *__restrict__ slot, const int *__restrict__ tmpl,
-                                                    const double *__restrict__ center, const int *__restrict__ t_s,
-                                                    const int *__restrict__ t_ny, const int64_t *__restrict__ t_yoff,
+__global__ __launch_bounds__(LEAF_BLOCK) void k_s2m(const int *__restrict__ gptr, const int64_t *__restrict__ start,
+                                                    const int64_t *__restrict__ end, const int64_t *__restrict__ slot,
+                                                    const int *__restrict__ tmpl, const double *__restrict__ center,
+                                                    const int *__restrict__ t_s, const int *__restrict__ t_ny,
+                                                    const int64_t *__restrict__ t_yoff,
                                                     const int64_t *__restrict__ t_woff, const double *__restrict__ tY,
                                                     const typename Cx<R>::T *__restrict__ tW,
                                                     const double *__restrict__ X, const double *__restrict__ Y,
                                                     const double *__restrict__ Z, const double *__restrict__ NX,
                                                     const double *__restrict__ NY, const double *__restrict__ NZ,
                                                     const double2 *__restrict__ dens,
-                                                    typename Cx<R>::T *__restrict__ od, double k, O c)
+                                                    typename Cx<R>::T *__restrict__ od, double k, O c, int max_ny)
 {
     using C = typename Cx<R>::T;
     extern __shared__ unsigned char shraw[];
-    C *phi = (C *)shraw;
-    const int task = blockIdx.x, tid = threadIdx.x;
-    const int lev = tmpl[task];
+    C *phi = (C *)shraw;  // [L2T_G][max_ny]
+    const int tid = threadIdx.x;
+    const int ta = gptr[blockIdx.x], ng = gptr[blockIdx.x + 1] - ta;
+    const int lev = tmpl[ta];
     const int s = t_s[lev], ny = t_ny[lev];
     const double *Yt = tY + t_yoff[lev];
-    const C *W = tW + t_woff[lev];
-    const double cx = center[3 * task], cy = center[3 * task + 1], cz = center[3 * task + 2];
-    const int64_t j0 = start[task], j1 = end[task];
-    for (int a = tid; a < ny; a += LEAF_BLOCK) {
-        const double ax = cx + Yt[3 * a], ay = cy + Yt[3 * a + 1], az = cz + Yt[3 * a + 2];
+    const C *W = tW + t_woff[lev];  // element (r, a) at r + a s
+    for (int e = tid; e < L2T_G * ny; e += LEAF_BLOCK) {
+        const int g = e / ny, a = e - g * ny;
         C acc = Cx<R>::mk(0, 0);
-        for (int64_t j = j0; j < j1; ++j) {
-            const C K = kernel_src<R>((R)(ax - X[j]), (R)(ay - Y[j]), (R)(az - Z[j]), (R)NX[j], (R)NY[j], (R)NZ[j],
-                                      (R)k, c);
-            acc = cadd(acc, cmul(K, from64<C>(dens[j])));
+        if (g < ng) {
+            const int task = ta + g;
+            const double ax = center[3 * task] + Yt[3 * a], ay = center[3 * task + 1] + Yt[3 * a + 1],
+                         az = center[3 * task + 2] + Yt[3 * a + 2];
+            const int64_t j1 = end[task];
+            for (int64_t j = start[task]; j < j1; ++j) {
+                const C K = kernel_src<R>((R)(ax - X[j]), (R)(ay - Y[j]), (R)(az - Z[j]), (R)NX[j], (R)NY[j],
+                                          (R)NZ[j], (R)k, c);
+                acc = cadd(acc, cmul(K, from64<C>(dens[j])));
+            }
         }
-        phi[a] = acc;
+        phi[g * max_ny + a] = acc;
     }
     __syncthreads();
-    const int64_t so = slot[task];
     for (int r = tid; r < s; r += LEAF_BLOCK) {
-        C acc = Cx<R>::mk(0, 0);
-        for (int a = 0; a < ny; ++a) acc = cadd(acc, cmul(W[r + (int64_t)a * s], phi[a]));
-        od[so + r] = cadd(od[so + r], acc);
+        C acc[L2T_G];
+#pragma unroll
+        for (int g = 0; g < L2T_G; ++g) acc[g] = Cx<R>::mk(0, 0);
+        for (int a = 0; a < ny; ++a) {
+            const C w = W[r + (int64_t)a * s];
+#pragma unroll
+            for (int g = 0; g < L2T_G; ++g) acc[g] = cadd(acc[g], cmul(w, phi[g * max_ny + a]));
+        }
+#pragma unroll
+        for (int g = 0; g < L2T_G; ++g)
+            if (g < ng) {
+                C *o = od + slot[ta + g] + r;
+                *o = cadd(*o, acc[g]);
+            }
     }
 }
 
-// L2T: incoming equivalent densities q = W^T y, then E_dn q at the targets.
+// L2T: a workgroup takes up to L2T_G leaves of one template.  First the
+// equivalent densities q_g = W^T y_g of every leaf (W read once per group,
+// transposed so consecutive threads read consecutive elements), then per
+// leaf the targets' sums over the equivalent points, with thread = (target t,
+// point slice j) and the slices added in a fixed order.
 template <typename R, typename O>
-__global__ __launch_bounds__(LEAF_BLOCK) void k_l2t(const int64_t *__restrict__ start, const int64_t *__restrict__ end,
-                                                    const int64_t *__restrict__ slot, const int *__restrict__ tmpl,
-                                                    const double *__restrict__ center, const int *__restrict__ t_s,
-                                                    const int *__restrict__ t_ny, const int64_t *__restrict__ t_yoff,
+__global__ __launch_bounds__(LEAF_BLOCK) void k_l2t(const int *__restrict__ gptr, const int64_t *__restrict__ start,
+                                                    const int64_t *__restrict__ end, const int64_t *__restrict__ slot,
+                                                    const int *__restrict__ tmpl, const double *__restrict__ center,
+                                                    const int *__restrict__ t_s, const int *__restrict__ t_ny,
+                                                    const int64_t *__restrict__ t_yoff,
                                                     const int64_t *__restrict__ t_woff, const double *__restrict__ tY,
-                                                    const typename Cx<R>::T *__restrict__ tW,
+                                                    const typename Cx<R>::T *__restrict__ tWt,
                                                     const double *__restrict__ X, const double *__restrict__ Y,
                                                     const double *__restrict__ Z, const double *__restrict__ NX,
                                                     const double *__restrict__ NY, const double *__restrict__ NZ,
                                                     const typename Cx<R>::T *__restrict__ id,
-                                                    double2 *__restrict__ res, double k, O c)
+                                                    double2 *__restrict__ res, double k, O c, int max_ny, int max_s)
 {
     using C = typename Cx<R>::T;
     extern __shared__ unsigned char shraw[];
-    C *q = (C *)shraw;
-    const int task = blockIdx.x, tid = threadIdx.x;
-    const int lev = tmpl[task];
+    C *q = (C *)shraw;                        // [L2T_G][max_ny]
+    C *xs = q + (size_t)L2T_G * max_ny;       // [L2T_G][max_s]
+    C *red = xs + (size_t)L2T_G * max_s;      // [LEAF_BLOCK]
+    double *ys = (double *)(red + LEAF_BLOCK);  // [3 max_ny]
+    const int tid = threadIdx.x;
+    const int ta = gptr[blockIdx.x], ng = gptr[blockIdx.x + 1] - ta;
+    const int lev = tmpl[ta];
     const int s = t_s[lev], ny = t_ny[lev];
     const double *Yt = tY + t_yoff[lev];
-    const C *W = tW + t_woff[lev];
-    const double cx = center[3 * task], cy = center[3 * task + 1], cz = center[3 * task + 2];
-    const int64_t so = slot[task];
+    const C *Wt = tWt + t_woff[lev];  // element (r, a) at a + r ny
+    for (int e = tid; e < L2T_G * s; e += LEAF_BLOCK) {
+        const int g = e / s, r = e - g * s;
+        xs[g * max_s + r] = g < ng ? id[slot[ta + g] + r] : Cx<R>::mk(0, 0);
+    }
+    for (int e = tid; e < 3 * ny; e += LEAF_BLOCK) ys[e] = Yt[e];
+    __syncthreads();
     for (int a = tid; a < ny; a += LEAF_BLOCK) {
-        C acc = Cx<R>::mk(0, 0);
-        for (int r = 0; r < s; ++r) acc = cadd(acc, cmul(W[r + (int64_t)a * s], id[so + r]));
-        q[a] = acc;
+        C acc[L2T_G];
+#pragma unroll
+        for (int g = 0; g < L2T_G; ++g) acc[g] = Cx<R>::mk(0, 0);
+        for (int r = 0; r < s; ++r) {
+            const C w = Wt[a + (int64_t)r * ny];
+#pragma unroll
+            for (int g = 0; g < L2T_G; ++g) acc[g] = cadd(acc[g], cmul(w, xs[g * max_s + r]));
+        }
+#pragma unroll
+        for (int g = 0; g < L2T_G; ++g)
+            if (g < ng) q[g * max_ny + a] = acc[g];
     }
     __syncthreads();
-    const int64_t i0 = start[task], i1 = end[task];
-    for (int64_t i = i0 + tid; i < i1; i += LEAF_BLOCK) {
-        const double xi = X[i], yi = Y[i], zi = Z[i];
-        const R nxi = (R)NX[i], nyi = (R)NY[i], nzi = (R)NZ[i];
-        C acc = Cx<R>::mk(0, 0);
-        for (int a = 0; a < ny; ++a) {
-            const C K = kernel_tgt<R>((R)(xi - (cx + Yt[3 * a])), (R)(yi - (cy + Yt[3 * a + 1])),
-                                      (R)(zi - (cz + Yt[3 * a + 2])), nxi, nyi, nzi, (R)k, c);
-            acc = cadd(acc, cmul(K, q[a]));
+    for (int g = 0; g < ng; ++g) {
+        const int task = ta + g;
+        const double cx = center[3 * task], cy = center[3 * task + 1], cz = center[3 * task + 2];
+        const C *qg = q + g * max_ny;
+        const int64_t i0 = start[task], i1 = end[task];
+        for (int64_t ib = i0; ib < i1; ib += LEAF_BLOCK) {
+            const int nt = (int)min((int64_t)LEAF_BLOCK, i1 - ib);
+            const int S = LEAF_BLOCK / nt;
+            const int j = tid / nt, t = tid - j * nt;
+            C acc = Cx<R>::mk(0, 0);
+            if (j < S) {
+                const int64_t i = ib + t;
+                const double xi = X[i] - cx, yi = Y[i] - cy, zi = Z[i] - cz;
+                const R nxi = (R)NX[i], nyi = (R)NY[i], nzi = (R)NZ[i];
+                for (int a = j; a < ny; a += S) {
+                    const C K = kernel_tgt<R>((R)(xi - ys[3 * a]), (R)(yi - ys[3 * a + 1]), (R)(zi - ys[3 * a + 2]),
+                                              nxi, nyi, nzi, (R)k, c);
+                    acc = cadd(acc, cmul(K, qg[a]));
+                }
+            }
+            red[tid] = acc;
+            __syncthreads();
+            if (tid < nt) {
+                C sum = red[tid];
+                for (int jj = 1; jj < S; ++jj) sum = cadd(sum, red[tid + jj * nt]);
+                res[ib + tid] = cadd(res[ib + tid], to64(sum));
+            }
+            __syncthreads();
         }
-        res[i] = cadd(res[i], to64(acc));
     }
+}
+
+// LDS of k_l2t: q and the local densities of L2T_G leaves, the slice sums,
+// the check points
+template <typename R>
+static size_t s2m_shm(const Plan &P)
+{
+    return sizeof(typename Cx<R>::T) * L2T_G * (size_t)std::max(P.max_Y_leaf, 1);
+}
+template <typename R>
+static size_t l2t_shm(const Plan &P)
+{
+    const size_t ny = std::max(P.max_Y_leaf, 1), s = std::max(P.max_s, 1);
+    return sizeof(typename Cx<R>::T) * (L2T_G * ny + L2T_G * s + LEAF_BLOCK) + sizeof(double) * 3 * ny;
 }
 
 // Batched segmented GEMV: out[o] += sum_e op(M_e) in[e]; one block per output slot.
@@ -1056,6 +1139,11 @@ static DLeaf upload_leaf(Device &D, const Plan &P, const std::vector<LeafTask> &
         c[3 * i + 1] = T[i].center[1];
         c[3 * i + 2] = T[i].center[2];
     }
+    std::vector<int> gp{0};
+    for (int i = 1; i <= L.n; ++i)
+        if (i == L.n || tm[i] != tm[gp.back()] || i - gp.back() == L2T_G) gp.push_back(i);
+    L.n_groups = (int)gp.size() - 1;
+    L.gptr = dupload(D, gp);
     L.start = dupload(D, s);
     L.end = dupload(D, e);
     L.slot = dupload(D, sl);
@@ -1165,7 +1253,7 @@ void device_upload(Plan &P)
         std::vector<int> ts(nlev, 0), tny(nlev, 0);
         std::vector<int64_t> yoff(nlev, 0), woff(nlev, 0);
         std::vector<double> Yall;
-        std::vector<double2> Wall;
+        std::vector<double2> Wall, Wtall;
         for (int l = 0; l < nlev; ++l) {
             const LevelTemplate &T = P.tmpl[l];
             ts[l] = T.s;
@@ -1174,6 +1262,12 @@ void device_upload(Plan &P)
             woff[l] = (int64_t)Wall.size();
             Yall.insert(Yall.end(), T.Y.begin(), T.Y.end());
             for (const cplx &v : T.W.a) Wall.push_back(make_double2(v.real(), v.imag()));
+            const int ny = (int)T.Y.size() / 3;
+            Wtall.insert(Wtall.end(), Wall.begin() + woff[l], Wall.end());
+            if ((int64_t)T.W.a.size() == (int64_t)T.s * ny)
+                for (int a = 0; a < ny; ++a)
+                    for (int r = 0; r < T.s; ++r)
+                        Wtall[woff[l] + a + (int64_t)r * ny] = Wall[woff[l] + r + (int64_t)a * T.s];
         }
         D.t_s = dupload(D, ts);
         D.t_ny = dupload(D, tny);
@@ -1181,6 +1275,7 @@ void device_upload(Plan &P)
         D.t_woff = dupload(D, woff);
         D.t_Y = dupload(D, Yall);
         D.t_W = dupload(D, Wall);
+        D.t_Wt = dupload(D, Wtall);
         std::vector<double2> mp(P.matpool.size());
         for (size_t i = 0; i < mp.size(); ++i) mp[i] = make_double2(P.matpool[i].real(), P.matpool[i].imag());
         D.mat = dupload(D, mp);
@@ -1327,6 +1422,23 @@ void device_upload(Plan &P)
         }
         D.s2m = upload_leaf(D, P, P.s2m_tasks);
         D.l2t = upload_leaf(D, P, P.l2t_tasks);
+        if (D.s2m.n && s2m_shm<double>(P) > 65536) {
+            if (s2m_shm<double>(P) > (size_t)maxsh) throw std::runtime_error("S2M templates too large for LDS");
+            HIP_CHECK(hipFuncSetAttribute((const void *)k_s2m<double, OpC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)s2m_shm<double>(P)));
+            HIP_CHECK(hipFuncSetAttribute((const void *)k_s2m<float, OpCf>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)s2m_shm<float>(P)));
+        }
+        if (D.l2t.n) {
+            const size_t lsh = l2t_shm<double>(P);
+            if (lsh > (size_t)maxsh) throw std::runtime_error("L2T templates too large for LDS");
+            if (lsh > 65536) {
+                HIP_CHECK(hipFuncSetAttribute((const void *)k_l2t<double, OpC>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lsh));
+                HIP_CHECK(hipFuncSetAttribute((const void *)k_l2t<float, OpCf>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2t_shm<float>(P)));
+            }
+        }
         D.n_od = P.out_total;
         D.n_id = P.in_total;
         D.prec = P.opt.precision;
@@ -1340,6 +1452,19 @@ void device_upload(Plan &P)
             for (int l = 0; l < nlev; ++l)
                 for (const cplx &v : P.tmpl[l].W.a) wf.push_back(make_float2((float)v.real(), (float)v.imag()));
             D.t_Wf = dupload(D, wf);
+            std::vector<float2> wtf(wf.size());
+            for (int l = 0, off = 0; l < nlev; ++l) {
+                const LevelTemplate &T = P.tmpl[l];
+                const int ny = (int)T.Y.size() / 3;
+                const bool full = (int64_t)T.W.a.size() == (int64_t)T.s * ny;
+                for (size_t e = 0; e < T.W.a.size(); ++e) {
+                    const size_t r = full ? e % T.s : 0, a = full ? e / T.s : e;
+                    const cplx v = T.W.a[e];
+                    wtf[off + (full ? a + r * ny : e)] = make_float2((float)v.real(), (float)v.imag());
+                }
+                off += (int)T.W.a.size();
+            }
+            D.t_Wtf = dupload(D, wtf);
             D.odf = dalloc<float2>(D, D.n_od);
             D.idf = dalloc<float2>(D, D.n_id);
         }
@@ -1462,19 +1587,38 @@ static void launch_slabs(const std::vector<DChunks> &S, void *part, const typena
     }
 }
 
+template <typename R, typename O>
+static void launch_s2m(Plan &P, Device &D, const O &c, const typename Cx<R>::T *tW, typename Cx<R>::T *od,
+                       hipStream_t st)
+{
+    if (!D.s2m.n) return;
+    hipLaunchKernelGGL((k_s2m<R, O>), dim3(D.s2m.n_groups), dim3(LEAF_BLOCK), s2m_shm<R>(P), st, D.s2m.gptr,
+                       D.s2m.start, D.s2m.end, D.s2m.slot, D.s2m.tmpl, D.s2m.center, D.t_s, D.t_ny, D.t_yoff,
+                       D.t_woff, D.t_Y, tW, D.x, D.y, D.z, D.nx, D.ny, D.nz, D.dens, od, P.k, c,
+                       std::max(P.max_Y_leaf, 1));
+}
+
+template <typename R, typename O>
+static void launch_l2t(Plan &P, Device &D, const O &c, const typename Cx<R>::T *tWt, const typename Cx<R>::T *id,
+                       hipStream_t st)
+{
+    if (!D.l2t.n) return;
+    hipLaunchKernelGGL((k_l2t<R, O>), dim3(D.l2t.n_groups), dim3(LEAF_BLOCK), l2t_shm<R>(P), st, D.l2t.gptr,
+                       D.l2t.start, D.l2t.end, D.l2t.slot, D.l2t.tmpl, D.l2t.center, D.t_s, D.t_ny, D.t_yoff,
+                       D.t_woff, D.t_Y, tWt, D.x, D.y, D.z, D.nx, D.ny, D.nz, id, D.res, P.k, c,
+                       std::max(P.max_Y_leaf, 1), std::max(P.max_s, 1));
+}
+
 // S2M .. L2T in working precision R (operator-chunk schedule)
 template <typename R, typename O>
 static void far_field_chunks(Plan &P, Device &D, const O &c, const typename Cx<R>::T *mat, const typename Cx<R>::T *tW,
-                             typename Cx<R>::T *od, typename Cx<R>::T *id, hipEvent_t *ev, hipStream_t st)
+                             const typename Cx<R>::T *tWt, typename Cx<R>::T *od, typename Cx<R>::T *id,
+                             hipEvent_t *ev, hipStream_t st)
 {
     using C = typename Cx<R>::T;
     if (D.n_od) hipLaunchKernelGGL(k_fill_zero<C>, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, od, D.n_od);
     if (D.n_id) hipLaunchKernelGGL(k_fill_zero<C>, dim3(nblk(D.n_id, 256)), dim3(256), 0, st, id, D.n_id);
-    const size_t shm_leaf = sizeof(C) * std::max(P.max_Y_leaf, 1);
-    if (D.s2m.n)
-        hipLaunchKernelGGL((k_s2m<R, O>), dim3(D.s2m.n), dim3(LEAF_BLOCK), shm_leaf, st, D.s2m.start, D.s2m.end,
-                           D.s2m.slot, D.s2m.tmpl, D.s2m.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, tW, D.x,
-                           D.y, D.z, D.nx, D.ny, D.nz, D.dens, od, P.k, c);
+    launch_s2m<R, O>(P, D, c, tW, od, st);
     if (ev) HIP_CHECK(hipEventRecord(ev[3], st));
     const bool slabs = D.m2l_mode == 3;
     for (int l = D.n_lev - 2; l >= 0; --l) {
@@ -1498,10 +1642,7 @@ static void far_field_chunks(Plan &P, Device &D, const O &c, const typename Cx<R
             launch_chunks<TAG_L2L, true, R>(D.l2lc[l], D.l2lc[l].cols, mat, id, id, st);
     }
     if (ev) HIP_CHECK(hipEventRecord(ev[6], st));
-    if (D.l2t.n)
-        hipLaunchKernelGGL((k_l2t<R, O>), dim3(D.l2t.n), dim3(LEAF_BLOCK), shm_leaf, st, D.l2t.start, D.l2t.end,
-                           D.l2t.slot, D.l2t.tmpl, D.l2t.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff, D.t_Y, tW, D.x,
-                           D.y, D.z, D.nx, D.ny, D.nz, id, D.res, P.k, c);
+    launch_l2t<R, O>(P, D, c, tWt, id, st);
 }
 
 void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st)
@@ -1526,17 +1667,13 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
     if (P.opt.far_field && f32) {
         const OpCf cf = {make_float2((float)c.c0.x, (float)c.c0.y), make_float2((float)c.c1.x, (float)c.c1.y),
                          make_float2((float)c.d0.x, (float)c.d0.y), make_float2((float)c.d1.x, (float)c.d1.y)};
-        far_field_chunks<float, OpCf>(P, D, cf, D.matf, D.t_Wf, D.odf, D.idf, ev, st);
+        far_field_chunks<float, OpCf>(P, D, cf, D.matf, D.t_Wf, D.t_Wtf, D.odf, D.idf, ev, st);
     } else if (P.opt.far_field && (D.m2l_mode == 0 || D.m2l_mode == 3)) {
-        far_field_chunks<double, OpC>(P, D, c, D.mat, D.t_W, D.od, D.id, ev, st);
+        far_field_chunks<double, OpC>(P, D, c, D.mat, D.t_W, D.t_Wt, D.od, D.id, ev, st);
     } else if (P.opt.far_field) {
         if (D.n_od) hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, D.od, D.n_od);
         if (D.n_id) hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_id, 256)), dim3(256), 0, st, D.id, D.n_id);
-        const size_t shm_leaf = sizeof(double2) * std::max(P.max_Y_leaf, 1);
-        if (D.s2m.n)
-            hipLaunchKernelGGL((k_s2m<double, OpC>), dim3(D.s2m.n), dim3(LEAF_BLOCK), shm_leaf, st, D.s2m.start,
-                               D.s2m.end, D.s2m.slot, D.s2m.tmpl, D.s2m.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff,
-                               D.t_Y, D.t_W, D.x, D.y, D.z, D.nx, D.ny, D.nz, D.dens, D.od, P.k, c);
+        launch_s2m<double, OpC>(P, D, c, D.t_W, D.od, st);
         if (tm) HIP_CHECK(hipEventRecord(ev[3], st));
         for (int l = D.n_lev - 2; l >= 0; --l) run_gemv<TAG_M2M>(D.m2m[l], D.mat, D.od, D.od, st);
         if (tm) HIP_CHECK(hipEventRecord(ev[4], st));
@@ -1557,10 +1694,7 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
         if (tm) HIP_CHECK(hipEventRecord(ev[5], st));
         for (int l = 1; l < D.n_lev; ++l) run_gemv<TAG_L2L>(D.l2l[l], D.mat, D.id, D.id, st);
         if (tm) HIP_CHECK(hipEventRecord(ev[6], st));
-        if (D.l2t.n)
-            hipLaunchKernelGGL((k_l2t<double, OpC>), dim3(D.l2t.n), dim3(LEAF_BLOCK), shm_leaf, st, D.l2t.start,
-                               D.l2t.end, D.l2t.slot, D.l2t.tmpl, D.l2t.center, D.t_s, D.t_ny, D.t_yoff, D.t_woff,
-                               D.t_Y, D.t_W, D.x, D.y, D.z, D.nx, D.ny, D.nz, D.id, D.res, P.k, c);
+        launch_l2t<double, OpC>(P, D, c, D.t_Wt, D.id, st);
     } else if (tm) {
         for (int e = 3; e <= 6; ++e) HIP_CHECK(hipEventRecord(ev[e], st));
     }

@@ -67,6 +67,8 @@ struct DLearn {
 
 struct DLeaf {
     int n = 0;
+    int n_groups = 0;          // groups of up to L2T_G consecutive tasks of one template
+    int *gptr = nullptr;       // group g: tasks [gptr[g], gptr[g + 1])
     int64_t *start = nullptr, *end = nullptr, *slot = nullptr;
     int *tmpl = nullptr;
     double *center = nullptr;  // n x 3
@@ -88,6 +90,7 @@ struct Device {
     int64_t *t_yoff = nullptr, *t_woff = nullptr;
     double *t_Y = nullptr;       // concatenated check points
     double2 *t_W = nullptr;      // concatenated W matrices
+    double2 *t_Wt = nullptr;     // the same, each transposed (element (r, a) at a + r |Y|)
     // translations
     double2 *mat = nullptr;
     std::vector<DGemv> m2m, m2l, l2l;  // per level
@@ -107,7 +110,7 @@ struct Device {
     double2 *res = nullptr;      // sorted result (N)
     double2 *od = nullptr, *id = nullptr;
     int prec = 0;                // 0 FP64, 1 FP32 far field and P2P
-    float2 *matf = nullptr, *t_Wf = nullptr, *odf = nullptr, *idf = nullptr;
+    float2 *matf = nullptr, *t_Wf = nullptr, *t_Wtf = nullptr, *odf = nullptr, *idf = nullptr;
     int64_t n_od = 0, n_id = 0;
     // near-field corrections (caller order, block CSR: 6 columns per element)
     DCorr corr, corrg;
