@@ -96,8 +96,9 @@ typedef struct {
     double coupling;    /* Burton-Miller coupling alpha = i * coupling / k (section 2.1,
                            eq. eq_bm); 0 -> 1, the value the paper uses.  -1 gives the
                            conjugate coupling (see bm_solve). */
-    int autotune;       /* 1 (default): at build, time 16 and 32 pairs per M2L chunk on the
-                           plan's own lists and keep the faster per level; 0: 16 */
+    int autotune;       /* 1 (default): at build, time 16 and 32 pairs per M2L, M2M and L2L
+                           chunk on the plan's own lists and keep the faster per translation
+                           and level (fda_stats: m2l_/m2m_/l2l_autotune); 0: 16 */
     int slab_mb;        /* scratch for per-pair translation results, MiB per slab; 0 -> 1024 */
 } fda_opts;
 

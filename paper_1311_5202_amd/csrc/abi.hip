@@ -231,15 +231,21 @@ int fda_stats(const fda_plan *plan, char *buf, size_t len)
                 if (T.n_tiles) tile = T.tile, chunk = T.chunk, shm = std::max(shm, T.shm);
             int maxsh = 0;
             (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, P.dev->device);
-            s += ", \"m2l_autotune\": [";
-            for (size_t q = 0; q < P.dev->autotune.size(); ++q) {
-                const auto &a = P.dev->autotune[q];
-                char buf[160];
-                std::snprintf(buf, sizeof buf, "%s{\"level\": %d, \"pairs_per_chunk\": %d, \"ms_16\": %.4f, \"ms_32\": %.4f}",
-                              q ? ", " : "", (int)a[0], (int)a[1], a[2], a[3]);
-                s += buf;
+            static const char *tune_keys[3] = {"m2l_autotune", "m2m_autotune", "l2l_autotune"};
+            for (int kind = 0; kind < 3; ++kind) {
+                s += std::string(", \"") + tune_keys[kind] + "\": [";
+                bool first = true;
+                for (const auto &a : P.dev->autotune) {
+                    if ((int)a[4] != kind) continue;
+                    char buf[160];
+                    std::snprintf(buf, sizeof buf,
+                                  "%s{\"level\": %d, \"pairs_per_chunk\": %d, \"ms_16\": %.4f, \"ms_32\": %.4f}",
+                                  first ? "" : ", ", (int)a[0], (int)a[1], a[2], a[3] < 1e29 ? a[3] : -1.0);
+                    s += buf;
+                    first = false;
+                }
+                s += "]";
             }
-            s += "]";
             s += ", \"m2l_mode\": " + std::to_string(P.dev->m2l_mode) + ", \"m2l_tile\": " + std::to_string(tile) +
                  ", \"m2l_chunk\": " + std::to_string(chunk) + ", \"m2l_lds_bytes\": " + std::to_string(shm) +
                  ", \"max_lds_per_block\": " + std::to_string(maxsh) + ", \"m2l_tiles\": [";

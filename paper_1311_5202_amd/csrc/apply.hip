@@ -820,17 +820,26 @@ __device__ __forceinline__ void mfma_tile(const typename Cx<R>::T *__restrict__ 
 #pragma unroll
                 for (int t = 0; t < NT; ++t) acc[u][t] = Mf<R>::mma(sgn * x[u], bp[4 * u * PW + 16 * t], acc[u][t]);
         }
-        for (; k0 < kmax; k0 += 4) {
-            const int K = k0 + k4, Kc = min(K, kmax - 1), jj = Kc >> 1, dd = Kc & 1;
-            const bool kok = K < kmax;
-            const R xv = arow[2 * jj * cs + (ci ^ dd)];
-            const R x = (rok && kok) ? xv : (R)0;
-            const R a = (ci == 0 && dd == 1) ? -x : x;
+        if (k0 < kmax) {
+            // the remaining < 4U inner indices in one masked step (all loads issued together)
+            const int j0 = (k0 + k4) >> 1;
+            R x[U], bv[U][NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const R bv = B[Kc * PW + 16 * t + i16];
-                acc[0][t] = Mf<R>::mma(a, kok ? bv : (R)0, acc[0][t]);
+            for (int u = 0; u < U; ++u) {
+                const int K = k0 + k4 + 4 * u;
+                const bool kok = K < kmax;
+                const R xv = arow[2 * (kok ? j0 + 2 * u : 0) * cs + sel];
+                x[u] = (rok && kok) ? xv : (R)0;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const R b = B[(kok ? K : 0) * PW + 16 * t + i16];
+                    bv[u][t] = kok ? b : (R)0;
+                }
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[u][t] = Mf<R>::mma(sgn * x[u], bv[u][t], acc[u][t]);
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t)
@@ -863,7 +872,7 @@ struct KSplit {
     __device__ KSplit(int r, int cols)
     {
         n_rt = (2 * r + 15) >> 4;
-        const int want = n_rt < M2LC_WAVES ? M2LC_WAVES / n_rt : 1, kmax = 2 * cols;
+        const int want = (n_rt > 0 && n_rt < M2LC_WAVES) ? M2LC_WAVES / n_rt : 1, kmax = 2 * cols;
         kstep = (((kmax + want - 1) / want) + 15) & ~15;
         ns = want > 1 ? (kmax + kstep - 1) / kstep : 1;
     }
@@ -1168,6 +1177,27 @@ static void free_chunks(Device &D, DChunks &c)
     c = DChunks();
 }
 
+// Dynamic LDS limit of every matrix-core chunk kernel instance, raised to at
+// least `bytes` (the default limit is 64 KiB).
+static void set_mfma_lds(Device &D, size_t bytes)
+{
+    if (bytes <= 65536 || bytes <= D.mfma_lds) return;
+    for (const void *f : {(const void *)k_chunks_mfma<double, false, 1, TAG_M2L>,
+                          (const void *)k_chunks_mfma<double, false, 1, TAG_M2M>,
+                          (const void *)k_chunks_mfma<double, true, 1, TAG_L2L>,
+                          (const void *)k_chunks_mfma<float, false, 1, TAG_M2L>,
+                          (const void *)k_chunks_mfma<float, false, 1, TAG_M2M>,
+                          (const void *)k_chunks_mfma<float, true, 1, TAG_L2L>,
+                          (const void *)k_chunks_mfma<double, false, 2, TAG_M2L>,
+                          (const void *)k_chunks_mfma<double, false, 2, TAG_M2M>,
+                          (const void *)k_chunks_mfma<double, true, 2, TAG_L2L>,
+                          (const void *)k_chunks_mfma<float, false, 2, TAG_M2L>,
+                          (const void *)k_chunks_mfma<float, false, 2, TAG_M2M>,
+                          (const void *)k_chunks_mfma<float, true, 2, TAG_L2L>})
+        HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    D.mfma_lds = bytes;
+}
+
 // Builder autotuner: for every M2L level, time the matrix-core chunk kernel
 // with 16 and with 32 pairs per chunk (one or two pair tiles per operator
 // element loaded) on this plan's own lists and keep the faster.  Both shapes
@@ -1182,17 +1212,28 @@ static void autotune_m2l(Plan &P, Device &D)
         hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_od, 256)), dim3(256), 0, 0, D.od, D.n_od);
         hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_id, 256)), dim3(256), 0, 0, D.id, D.n_id);
     }
+    int maxsh = 65536;
+    (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, D.device);
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
-    auto time = [&](const std::vector<DChunks> &S) {
+    // kind 0: M2L (od -> id), 1: M2M (od -> od), 2: L2L (id -> id, transposed operators)
+    auto launch = [&](int kind, const std::vector<DChunks> &S) {
+        if (f32) {
+            if (kind == 0) launch_slabs<TAG_M2L, false, float>(S, D.part, D.matf, D.odf, D.idf, 0);
+            if (kind == 1) launch_slabs<TAG_M2M, false, float>(S, D.part, D.matf, D.odf, D.odf, 0);
+            if (kind == 2) launch_slabs<TAG_L2L, true, float>(S, D.part, D.matf, D.idf, D.idf, 0);
+        } else {
+            if (kind == 0) launch_slabs<TAG_M2L, false, double>(S, D.part, D.mat, D.od, D.id, 0);
+            if (kind == 1) launch_slabs<TAG_M2M, false, double>(S, D.part, D.mat, D.od, D.od, 0);
+            if (kind == 2) launch_slabs<TAG_L2L, true, double>(S, D.part, D.mat, D.id, D.id, 0);
+        }
+    };
+    auto time = [&](int kind, const std::vector<DChunks> &S) {
         float best = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
             HIP_CHECK(hipEventRecord(e0, 0));
-            if (f32)
-                launch_slabs<TAG_M2L, false, float>(S, D.part, D.matf, D.odf, D.idf, 0);
-            else
-                launch_slabs<TAG_M2L, false, double>(S, D.part, D.mat, D.od, D.id, 0);
+            launch(kind, S);
             HIP_CHECK(hipEventRecord(e1, 0));
             HIP_CHECK(hipEventSynchronize(e1));
             float ms = 0;
@@ -1201,19 +1242,32 @@ static void autotune_m2l(Plan &P, Device &D)
         }
         return (double)best;
     };
-    for (int l = 0; l < (int)D.m2ls.size(); ++l) {
-        if (D.m2ls[l].empty()) continue;
-        const GemvList &G = P.m2l_lists[l];
-        std::vector<DChunks> alt;
-        for (const M2LChunks &C : build_chunk_slabs(G, 2 * M2LC_CH, slab_entries(G, P.opt.slab_mb))) alt.push_back(upload_chunks(D, C));
-        const double t16 = time(D.m2ls[l]), t32 = time(alt);
-        const bool take = t32 < t16;
-        if (take) std::swap(D.m2ls[l], alt);
-        for (DChunks &c : alt) free_chunks(D, c);
-        D.autotune.push_back({(double)l, (double)(take ? 2 * M2LC_CH : M2LC_CH), t16, t32});
-        if (P.opt.verbose) {
-            std::fprintf(stderr, "[fdbem] autotune M2L level %d: 16 pairs %.3f ms, 32 pairs %.3f ms\n", l, t16, t32);
-            std::fflush(stderr);
+    static const char *names[3] = {"M2L", "M2M", "L2L"};
+    for (int kind = 0; kind < 3; ++kind) {
+        std::vector<std::vector<DChunks>> &slabs = kind == 0 ? D.m2ls : kind == 1 ? D.m2ms : D.l2ls;
+        const std::vector<GemvList> &lists = kind == 0 ? P.m2l_lists : kind == 1 ? P.m2m_lists : P.l2l_lists;
+        for (int l = 0; l < (int)slabs.size(); ++l) {
+            if (slabs[l].empty()) continue;
+            const GemvList &G = lists[l];
+            std::vector<DChunks> alt;
+            for (const M2LChunks &C : build_chunk_slabs(G, 2 * M2LC_CH, slab_entries(G, P.opt.slab_mb)))
+                alt.push_back(upload_chunks(D, C));
+            size_t need = 0;
+            for (const DChunks &c : alt) need = std::max(need, mfma_shm(c));
+            double t16 = time(kind, slabs[l]), t32 = 1e30;
+            if (need <= (size_t)maxsh) {
+                set_mfma_lds(D, need);
+                t32 = time(kind, alt);
+            }
+            const bool take = t32 < t16;
+            if (take) std::swap(slabs[l], alt);
+            for (DChunks &c : alt) free_chunks(D, c);
+            D.autotune.push_back({(double)l, (double)(take ? 2 * M2LC_CH : M2LC_CH), t16, t32, (double)kind});
+            if (P.opt.verbose) {
+                std::fprintf(stderr, "[fdbem] autotune %s level %d: 16 pairs %.3f ms, 32 pairs %.3f ms\n", names[kind], l,
+                             t16, t32);
+                std::fflush(stderr);
+            }
         }
     }
     (void)hipEventDestroy(e0);
@@ -1321,21 +1375,7 @@ void device_upload(Plan &P)
                 for (const auto &lv : *v)
                     for (const DChunks &c : lv) mf = std::max(mf, mfma_shm(c));
             if (mf > (size_t)maxsh) throw std::runtime_error("translation operator too large for LDS");
-            if (mf > 65536)
-                for (const void *f :
-                     {(const void *)k_chunks_mfma<double, false, 1, TAG_M2L>,
-                      (const void *)k_chunks_mfma<double, false, 1, TAG_M2M>,
-                      (const void *)k_chunks_mfma<double, true, 1, TAG_L2L>,
-                      (const void *)k_chunks_mfma<float, false, 1, TAG_M2L>,
-                      (const void *)k_chunks_mfma<float, false, 1, TAG_M2M>,
-                      (const void *)k_chunks_mfma<float, true, 1, TAG_L2L>,
-                      (const void *)k_chunks_mfma<double, false, 2, TAG_M2L>,
-                      (const void *)k_chunks_mfma<double, false, 2, TAG_M2M>,
-                      (const void *)k_chunks_mfma<double, true, 2, TAG_L2L>,
-                      (const void *)k_chunks_mfma<float, false, 2, TAG_M2L>,
-                      (const void *)k_chunks_mfma<float, false, 2, TAG_M2M>,
-                      (const void *)k_chunks_mfma<float, true, 2, TAG_L2L>})
-                    HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mf));
+            set_mfma_lds(D, mf);
             D.part_bytes = part;
             if (part) D.part = dalloc<double2>(D, part / sizeof(double2));
         }

@@ -129,7 +129,9 @@ struct Device {
         void *out = nullptr;
     };
     int use_graph = 0;
-    std::vector<std::array<double, 4>> autotune;   // per tuned level: level, pairs per chunk, ms(16), ms(32)
+    // per tuned (translation, level): level, pairs per chunk, ms(16), ms(32), kind (0 M2L, 1 M2M, 2 L2L)
+    std::vector<std::array<double, 5>> autotune;
+    size_t mfma_lds = 65536;   // dynamic LDS limit set on the chunk kernels
     hipStream_t cap = nullptr;
     std::vector<GraphEntry> graphs;
     // timing

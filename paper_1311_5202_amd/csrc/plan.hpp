@@ -30,7 +30,7 @@ struct Options {
     int corrections = 1;     // build local corrections when elements are supplied
     int verbose = 0;
     double coupling = 1.0;   // Burton-Miller alpha = i coupling / k
-    int autotune = 1;        // time the M2L chunk shapes on the plan and keep the faster
+    int autotune = 1;        // time the M2L/M2M/L2L chunk shapes on the plan and keep the faster
     int slab_mb = 1024;      // scratch of per-pair translation results per slab (MiB)
     // k of the coupling: alpha = i / alpha_k()
     double alpha_k(double k) const { return k / coupling; }

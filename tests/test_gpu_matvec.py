@@ -179,8 +179,9 @@ def test_table1_accuracy_against_paper(torch, eps):
 
 
 def test_autotuned_chunk_shapes_give_identical_results(torch):
-    """The builder's M2L autotuner picks 16 or 32 pairs per chunk per level;
-    either shape gives bitwise the same mat-vec, and the choice is reported."""
+    """The builder's autotuner picks 16 or 32 pairs per chunk per level for
+    M2L, M2M and L2L; either shape gives bitwise the same mat-vec, and the
+    choices are reported."""
     import paper_1311_5202_amd as fdb
 
     _, pts, nrm, w = _geom(16)
@@ -188,11 +189,14 @@ def test_autotuned_chunk_shapes_give_identical_results(torch):
     u = torch.from_numpy(synth.random_densities(len(w), 5)).cuda()
     ref_plan = fdb.build(pts, nrm, w, k, 1e-4, autotune=0)
     ref = ref_plan.matvec(u, "RAW_H")
-    assert ref_plan.stats()["m2l_autotune"] == []
+    st0 = ref_plan.stats()
+    assert st0["m2l_autotune"] == [] and st0["m2m_autotune"] == [] and st0["l2l_autotune"] == []
     ref_plan.close()
     plan = fdb.build(pts, nrm, w, k, 1e-4, autotune=1)
-    tuned = plan.stats()["m2l_autotune"]
-    print("[autotune]", tuned, flush=True)
-    assert tuned and all(t["pairs_per_chunk"] in (16, 32) for t in tuned)
+    st = plan.stats()
+    for key in ("m2l_autotune", "m2m_autotune", "l2l_autotune"):
+        tuned = st[key]
+        print("[autotune]", key, tuned, flush=True)
+        assert tuned and all(t["pairs_per_chunk"] in (16, 32) for t in tuned), key
     assert torch.equal(plan.matvec(u, "RAW_H"), ref)
     plan.close()
