@@ -200,3 +200,29 @@ def test_autotuned_chunk_shapes_give_identical_results(torch):
         assert tuned and all(t["pairs_per_chunk"] in (16, 32) for t in tuned), key
     assert torch.equal(plan.matvec(u, "RAW_H"), ref)
     plan.close()
+
+
+@pytest.mark.parametrize("shape", ["ellipsoid", "star"])
+def test_fda_adaptive_surfaces_sampled_rows(torch, shape):
+    """Non-spherical surfaces (prolate ellipsoid 1:1:4, seeded star-shaped
+    surface) give adaptive trees whose leaves sit on several levels, so the
+    grouped S2M/L2T kernels see groups of different templates; 300 seeded
+    rows of every raw operator against the oracle."""
+    import paper_1311_5202_amd as fdb
+
+    el = synth.ellipsoid(16, 4.0) if shape == "ellipsoid" else synth.star_surface(16, 3)
+    pts, nrm, w = fdb.nystrom_nodes(el)
+    k = 20.0
+    print(f"[adaptive] {shape} N={len(w)} k={k}", flush=True)
+    plan = fdb.build(pts, nrm, w, k, 1e-4, precision="both")
+    u = synth.random_densities(len(w), 8)
+    ud = torch.from_numpy(u).cuda()
+    rows = np.sort(np.random.default_rng(9).choice(len(w), 300, replace=False))
+    for op, oop in OPS:
+        ref = oracle.dense_rows(pts, nrm, w, u, k, oop, rows=rows)
+        for fp32 in (False, True):
+            got = plan.matvec(ud, op, fp32=fp32).cpu().numpy()[rows]
+            err = oracle.rel_l2(got, ref)
+            print(shape, op, "fp32" if fp32 else "fp64", err, flush=True)
+            assert err <= 1e-4, (op, fp32)
+    plan.close()
