@@ -193,11 +193,12 @@ __global__ void k_permute_out(const double2 *__restrict__ res, const int64_t *__
     out[j] = v;
 }
 
-// Near field.  One 64-lane wavefront per target leaf: lane = (target t,
-// source slice q) with ntp = next power of two >= targets in the leaf and
-// 64/ntp slices, so small leaves still fill the wavefront; the slices are
-// summed with cross-lane shuffles.  The kernel shape is a template parameter
-// so every operator evaluates only its nonzero terms.
+// Near field.  One 64-lane wavefront per target leaf: lane = t + nt q for
+// target t of the nt targets and source slice q of S = 64 / nt, so small
+// leaves still fill the wavefront; each lane takes two sources per step, and
+// the slices are added in order q = 0, 1, .. with cross-lane shuffles.  The
+// kernel shape is a template parameter so every operator evaluates only its
+// nonzero terms.
 struct PN {
     double x, y, z, nx, ny, nz, pad0, pad1;
 };
