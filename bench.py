@@ -439,7 +439,8 @@ def main() -> int:
     p2p_roof = {"bound": "valu", "kernel": "P2P (near-field point sums)",
                 "achieved": p2p_flops / (phases["p2p"] * 1e-3) / 1e12 if phases["p2p"] > 0 else 0.0,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "flops_per_pair": P2P_FLOPS_PER_PAIR,
-                "pairs": st["p2p_pairs"]}
+                "pairs": st["p2p_pairs"],
+                "pairs_per_s": st["p2p_pairs"] / (phases["p2p"] * 1e-3) if phases["p2p"] > 0 else 0.0}
     p2p_roof["frac"] = p2p_roof["achieved"] / p2p_roof["peak"]
     res = {
         "metric": "FDA matvecs/s (Burton-Miller H operator)",
