@@ -38,14 +38,3 @@ def corrected_rows(elements, u, k, op="H", rows=None, free_term=None, rel_tol=1e
       ctypes.c_double(free_term), ctypes.c_double(rel_tol), out.ctypes.data_as(dp))
     return out
 
-
-def corrected_matrix(elements, k, op="H", free_term=None):
-    """Dense corrected operator (columns by unit vectors; small meshes only)."""
-    el = np.asarray(elements).reshape(-1, 6, 3)
-    n = 6 * el.shape[0]
-    A = np.empty((n, n), dtype=np.complex128)
-    for j in range(n):
-        e = np.zeros(n, dtype=np.complex128)
-        e[j] = 1.0
-        A[:, j] = corrected_rows(el, e, k, op, free_term=free_term)
-    return A

@@ -129,3 +129,43 @@ def test_bilinear_reciprocity_between_calls(oracle_lib):
     Hu = oracle_lib.dense_rows(pts, nrm, w, u, k, "HS")
     Ha = oracle_lib.dense_rows(pts, nrm, w, a, k, "HS")
     assert abs(a @ Hu - u @ Ha) < 1e-11 * abs(a @ Hu)
+
+
+def test_dense_matrix_structure(oracle_lib):
+    """dense_matrix against the kernel identities rather than itself: weights
+    sit on the columns (source side), the diagonal is zero, the H kernel is
+    symmetric under exchange of the two points with their normals, and the
+    G-kernel matrix is the transpose of the Table-1 kernel matrix (since
+    dG/dn_x(x,y) = dG/dn_y(y,x)), as the double-layer matrix is of the
+    adjoint one, while the hypersingular kernel alone is symmetric; its
+    product with u reproduces the independently accumulated dense_rows."""
+    rng = np.random.default_rng(21)
+    n, k = 40, 3.5
+    pts = rng.standard_normal((n, 3))
+    nrm = rng.standard_normal((n, 3)); nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    w = rng.uniform(0.2, 2.0, n)
+    u = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    H = oracle_lib.dense_matrix(pts, nrm, w, k, "H")
+    G = oracle_lib.dense_matrix(pts, nrm, w, k, "G")
+    T1 = oracle_lib.dense_matrix(pts, nrm, w, k, "T1")
+    assert np.all(np.diag(H) == 0) and np.all(np.diag(G) == 0)
+    Khs = oracle_lib.dense_matrix(pts, nrm, w, k, "HS") / w[None, :]
+    assert np.allclose(Khs, Khs.T, rtol=1e-12, atol=0)
+    D = oracle_lib.dense_matrix(pts, nrm, w, k, "D") / w[None, :]
+    M = oracle_lib.dense_matrix(pts, nrm, w, k, "M") / w[None, :]
+    assert np.allclose(D, M.T, rtol=1e-12, atol=0)
+    assert np.allclose(H / w[None, :], D + 1j / k * Khs, rtol=1e-12, atol=0)
+    assert np.allclose(G / w[None, :], (T1 / w[None, :]).T, rtol=1e-12, atol=0)
+    # one entry against the symbolic kernels (row/column orientation)
+    import mpmath
+    fs = _sympy_kernels()
+    i, j = 3, 17
+    args = [mpmath.mpf(float(v)) for v in (*pts[i], *nrm[i], *pts[j], *nrm[j])] + [mpmath.mpf(k)]
+    Gv, Gy, Gx, Gxy = (complex(f(*args)) for f in fs)
+    assert abs(H[i, j] - w[j] * (Gy + 1j / k * Gxy)) < 1e-12 * abs(H[i, j])
+    assert abs(G[i, j] - w[j] * (Gv + 1j / k * Gx)) < 1e-12 * abs(G[i, j])
+    for op, M in (("H", H), ("G", G), ("T1", T1)):
+        rows = oracle_lib.dense_rows(pts, nrm, w, u, k, op)
+        assert np.allclose(M @ u, rows, rtol=1e-12, atol=1e-14)
+    sub = np.array([5, 0, 39])
+    assert np.array_equal(oracle_lib.dense_matrix(pts, nrm, w, k, "H", rows=sub), H[sub])

@@ -104,3 +104,89 @@ def test_pulsating_sphere_from_spectra():
         assert abs(u - mie.pulsating_sphere(k)) < 1e-12
         # CBIE alone is singular at the characteristic frequencies k = n pi
     assert abs(mie.sphere_spectra(2 * np.pi, 0)["CBIE"]) < 1e-12
+
+
+# ---- the series at the wavenumbers of the large runs (section 5.3: k = 157.1
+# for the paper's 4M-node sphere, k = 500 for kD = 1000) ---------------------
+HIGH_K = [157.1, 500.0]
+
+
+@pytest.mark.parametrize("k", HIGH_K)
+def test_wronskian_over_the_whole_truncated_series(k):
+    """j_l h_l' - j_l' h_l = i / k^2 for every l the surface series uses."""
+    l = np.arange(0, mie.default_lmax(k) + 1)
+    j, jp = spherical_jn(l, k), spherical_jn(l, k, True)
+    h, hp = mie.sph_hankel1(l, k), mie.sph_hankel1(l, k, True)
+    assert np.allclose(j * hp - jp * h, 1j / k**2, rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("k", HIGH_K)
+def test_neumann_condition_at_high_k(k):
+    """du/dr = 0 on r = 1 by a fourth-order central difference of the full
+    series (analytic in r, so it can be evaluated just inside the sphere)."""
+    ct = np.cos(np.linspace(0, np.pi, 11))
+    h = 2e-6
+    f = {s: mie.mie_hard_total_field(k, np.full(ct.shape, 1 + s * h), ct, lmax=mie.default_lmax(k))
+         for s in (-2, -1, 0, 1, 2)}
+    dudr = (-f[2] + 8 * f[1] - 8 * f[-1] + f[-2]) / (12 * h)
+    scale = k * np.max(np.abs(f[0]))
+    assert np.max(np.abs(dudr)) < 1e-6 * scale
+    # the same derivative of the incident wave alone is of order k |u|
+    uinc = lambda r: np.exp(1j * k * r * ct)
+    dinc = (-uinc(1 + 2 * h) + 8 * uinc(1 + h) - 8 * uinc(1 - h) + uinc(1 - 2 * h)) / (12 * h)
+    assert np.max(np.abs(dinc)) > 0.5 * k
+    assert np.allclose(f[0], mie.mie_hard_total_surface(k, ct), rtol=1e-9, atol=1e-11)
+
+
+@pytest.mark.parametrize("k", HIGH_K)
+def test_series_tail_converged(k):
+    """Extending the truncated series by 100 terms changes nothing, and the
+    surface field equals the Wronskian form (i/k^2) sum i^l (2l+1) P_l / h_l'
+    that uses h_l' alone."""
+    ct = np.cos(np.linspace(0, np.pi, 201))
+    L = mie.default_lmax(k)
+    u = mie.mie_hard_total_surface(k, ct)
+    u_more = mie.mie_hard_total_surface(k, ct, lmax=L + 100)
+    assert np.max(np.abs(u - u_more)) < 1e-12 * np.max(np.abs(u))
+    l = np.arange(L + 1)
+    alt = (1j / k**2) * ((1j ** l) * (2 * l + 1) / mie.sph_hankel1(l, k, True)) @ mie.legendre_table(L, ct)
+    assert np.allclose(u, alt, rtol=1e-8, atol=1e-9)
+
+
+@pytest.mark.parametrize("k", HIGH_K)
+def test_geometric_optics_limit(k):
+    """At ka >> 1 the illuminated pole of a rigid sphere sees the incident
+    wave plus its specular reflection (reflection coefficient +1): |u| -> 2
+    with O(1/k) corrections; the shadow side is far weaker than the lit side."""
+    u = mie.mie_hard_total_surface(k, np.array([-1.0, -0.999, 0.5]))
+    assert abs(abs(u[0]) - 2.0) < 10.0 / k
+    assert abs(abs(u[1]) - 2.0) < 10.0 / k
+    assert abs(u[0] / np.exp(-1j * k) - 2.0) < 10.0 / k   # phase of the incident wave at z = -1
+    assert abs(u[2]) < 0.5
+
+
+@pytest.mark.parametrize("k", HIGH_K)
+def test_outgoing_far_field_and_optical_theorem(k):
+    """Far from the sphere the scattered field radiates (du_s/dr = ik u_s to
+    O(1/kr)), and energy is conserved: the extinction (4 pi / k) Im f(0)
+    equals the scattered power integrated over the sphere at infinity, with
+    f the far-field amplitude u_s ~ f exp(ikr)/r.  |f|^2 is a polynomial of
+    degree 2 lmax in cos(theta), so Gauss-Legendre with lmax + 2 nodes
+    integrates it exactly."""
+    L = mie.default_lmax(k)
+    R = 1e9
+    x, wq = np.polynomial.legendre.leggauss(L + 2)
+    us = mie.mie_hard_scattered(k, np.full(x.shape, R), x)
+    f = us * R * np.exp(-1j * k * R)
+    sigma_sc = 2 * np.pi * np.sum(wq * np.abs(f) ** 2)
+    f0 = mie.mie_hard_scattered(k, np.array([R]), np.array([1.0]))[0] * R * np.exp(-1j * k * R)
+    sigma_ext = 4 * np.pi / k * f0.imag
+    assert abs(sigma_sc - sigma_ext) < 1e-6 * sigma_ext
+    # geometric cross-section limit of a hard sphere: 2 pi a^2 (extinction paradox)
+    assert abs(sigma_ext / (2 * np.pi) - 1.0) < 0.1
+    r0 = 1e5
+    d = 1e-3 / k
+    ct = np.array([0.3])
+    ud = (mie.mie_hard_scattered(k, np.array([r0 + d]), ct) - mie.mie_hard_scattered(k, np.array([r0 - d]), ct)) / (2 * d)
+    u0 = mie.mie_hard_scattered(k, np.array([r0]), ct)
+    assert abs(ud[0] / (1j * k * u0[0]) - 1.0) < 1e-3
