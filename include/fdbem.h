@@ -43,7 +43,7 @@ enum {
 };
 
 /* Operators applied by fda_matvec (section 2.2 eqs. eq_hmat, eq_gmat, kcorrection,
- * section 4.1 eq. eq_sum).  w_j are the quadrature weights of the geometry. */
+ * section 5.1 eq. eq_sum).  w_j are the quadrature weights of the geometry. */
 enum {
     FDA_OP_RAW_H = 0,  /* p_i = sum_{j!=i} w_j [dG/dn_y + alpha d2G/dn_x dn_y](x_i,y_j) u_j */
     FDA_OP_RAW_G = 1,  /* p_i = sum_{j!=i} w_j [G + alpha dG/dn_x](x_i,y_j) u_j              */
@@ -127,7 +127,8 @@ int bem_near_correction(int64_t n_elem, const double *elem, const double *pts, c
                         double *val);
 
 /* Build a plan on the current HIP device: octree and lists (section 3.1.1),
- * point templates and pseudo-inverses (section 3.1.2, eqs. eq_svdr/eq_invr),
+ * point templates (section 3.1.2), their pseudo-inverses (section 4.1, eqs.
+ * eq_svdr/eq_invr),
  * compressed translation operators (section 4.1, eqs. eq_cmps..eq_cmpt),
  * low-rank M2L factors (eq. eq_lrdk) and, with elements, the locally
  * corrected near field (section 2.2).  k > 0 is the wavenumber, eps in
@@ -152,7 +153,7 @@ int fda_matvec(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *
 int bm_solve(fda_plan *plan, int op, const void *rhs_dev, double tol, int maxit, int restart, int precond,
              void *x_dev, int *iters_out, double *relres_out, double *resid_hist, void *hip_stream);
 
-/* Right-hand side of the sound-hard problem (section 4.3): incident plane
+/* Right-hand side of the sound-hard problem (section 5.3): incident plane
  * wave u_inc = exp(i k x.d) with unit direction d[3];
  * b_i = u_inc(x_i) + alpha du_inc/dn_x(x_i).  rhs_dev: complex128[N]. */
 int fda_rhs_plane_wave(fda_plan *plan, const double d[3], void *rhs_dev, void *hip_stream);

@@ -4,7 +4,7 @@ Plain, slow, FP64 CPU implementations of what the GPU path computes:
 
 * ``kernels`` / ``dense_rows`` / ``dense_matrix``: the Helmholtz fundamental
   solution and its normal derivatives, and the straightforward point-kernel
-  summation (paper section 2, eqs. fundsol, eq_hmat, eq_gmat; section 4.1,
+  summation (paper section 2, eqs. fundsol, eq_hmat, eq_gmat; section 5.1,
   eq. eq_sum) -- the exact result the fast directional algorithm reaches to
   its controlling accuracy.
 * ``quadrature``: the Nystrom nodes, normals and weights (section 2.2).
@@ -39,7 +39,7 @@ def op_coefficients(op: str, k: float):
     table = {
         "H": (0.0, 1.0, 1.0, alpha),      # eq. eq_hmat
         "G": (1.0, 0.0, 1.0, alpha),      # eq. eq_gmat
-        "T1": (1.0, alpha, 1.0, 0.0),     # eq. eq_sum (section 4.1)
+        "T1": (1.0, alpha, 1.0, 0.0),     # eq. eq_sum (section 5.1)
         "S": (1.0, 0.0, 1.0, 0.0),
         "D": (0.0, 1.0, 1.0, 0.0),
         "M": (1.0, 0.0, 0.0, 1.0),
@@ -104,7 +104,7 @@ def num_threads() -> int:
 
 
 def rel_l2(a, b) -> float:
-    """Relative L2 error ||a - b|| / ||b|| (the error measure of section 4.1)."""
+    """Relative L2 error ||a - b|| / ||b|| (the error measure of section 5.1)."""
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))

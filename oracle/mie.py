@@ -1,13 +1,13 @@
 """Analytic sphere solutions (test infrastructure only).
 
-* Plane-wave scattering by a sound-hard sphere of radius 1 (section 4.3):
+* Plane-wave scattering by a sound-hard sphere of radius 1 (section 5.3):
   separation of variables with u_inc = exp(ik x.d) = sum_l i^l (2l+1)
   j_l(kr) P_l(cos t) and an outgoing scattered part sum_l a_l h_l(kr)
   P_l(cos t); the Neumann condition du/dr = 0 at r = 1 fixes
   a_l = -i^l (2l+1) j_l'(k) / h_l'(k).  With G = exp(ikr)/(4 pi r) the
   outgoing Hankel function is h_l = h_l^(1) = j_l + i y_l (the paper writes
   "second kind"; with its exp(ikr) convention only the first kind radiates).
-* Pulsating sphere (section 4.2): q = 1 with the normal into the body gives
+* Pulsating sphere (section 5.2): q = 1 with the normal into the body gives
   u = 1 / (1 - ik) on the surface.
 * Eigenvalues of the layer operators of eq. operator on the unit sphere for
   the Legendre densities P_l(cos t), with the normal into the body, from the

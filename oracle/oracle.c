@@ -6,7 +6,7 @@
  * product library never links, loads or imports anything here, and nothing
  * here is shared with the GPU path.
  *
- * What it computes (paper section 2 and the summation of section 4.1):
+ * What it computes (paper section 2 and the summation of section 5.1):
  *   - the fundamental solution G = exp(ikr)/(4 pi r) of the Helmholtz
  *     equation and its normal derivatives dG/dn_y, dG/dn_x, d2G/dn_x dn_y
  *     (eq. fundsol and the operators of eq. operator), obtained by direct
@@ -15,7 +15,7 @@
  *     kernel K = (c0 + c1 d/dn_y)(d0 + d1 d/dn_x) G: with (c0,c1,d0,d1) =
  *     (0,1,1,alpha) this is the H matrix row of eq. eq_hmat, (1,0,1,alpha)
  *     the G matrix row of eq. eq_gmat, (1,alpha,1,0) the test kernel of the
- *     particle summation of section 4.1 (eq. eq_sum).  This is the
+ *     particle summation of section 5.1 (eq. eq_sum).  This is the
  *     "straightforward summation" the paper compares its fast algorithm with.
  *
  * Parity pins live in tests/test_oracle_*.py.

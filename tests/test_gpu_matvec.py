@@ -1,5 +1,5 @@
 """GPU parity of the fast directional mat-vec against the oracle's dense
-FP64 sums (section 4.1 error measure: relative L2 over target rows)."""
+FP64 sums (section 5.1 error measure: relative L2 over target rows)."""
 import numpy as np
 import pytest
 
@@ -152,7 +152,7 @@ def test_fp32_far_and_near_field(torch):
 
 @pytest.mark.parametrize("eps", [1e-4, 1e-6])
 def test_table1_accuracy_against_paper(torch, eps):
-    """Table-1 summation (section 4.1, eq. eq_sum) at the table's smallest size:
+    """Table-1 summation (section 5.1, eq. eq_sum) at the table's smallest size:
     N ~ 73,728 nodes at about 20 per wavelength, k = 8 pi, 200 seeded targets.
     The error must not exceed the paper's improved-FDA value by more than 2x
     (tests/golden/table1_eps_a.json)."""

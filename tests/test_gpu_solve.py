@@ -1,5 +1,5 @@
 """GPU Burton-Miller operator and GMRES solves (section 2.2 eq. Axb, section
-4.2 radiation and section 4.3 scattering checks) against the oracle and the
+5.2 radiation and section 5.3 scattering checks) against the oracle and the
 analytic sphere solutions."""
 import numpy as np
 import pytest
@@ -77,7 +77,7 @@ def test_plane_wave_scattering_solve(torch):
 
 def test_pulsating_sphere_at_characteristic_frequency(torch):
     """q = 1, k = 2 pi: (1/2 + D + alpha H) u = (S + alpha M) q - alpha q / 2,
-    closed form u = 1/(1 - ik) (section 4.2); plain CBIE fails at this k."""
+    closed form u = 1/(1 - ik) (section 5.2); plain CBIE fails at this k."""
     k = 2 * np.pi
     el, pts, nrm, w, plan = _plan(8, k, corrections=3)
     q = torch.ones(len(w), dtype=torch.complex128, device="cuda")

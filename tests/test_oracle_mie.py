@@ -1,4 +1,4 @@
-"""Pins of the analytic sphere solutions (sections 4.2 and 4.3)."""
+"""Pins of the analytic sphere solutions (sections 5.2 and 5.3)."""
 import numpy as np
 import pytest
 from scipy import integrate
@@ -29,7 +29,7 @@ def test_mie_satisfies_neumann_condition(k):
 
 
 def test_mie_paper_series_form():
-    """u = u_inc + sum_m [-i^m (2m+1) j'_m/h'_m] h_m P_m on r = 1 (section 4.3)."""
+    """u = u_inc + sum_m [-i^m (2m+1) j'_m/h'_m] h_m P_m on r = 1 (section 5.3)."""
     k = 5.0
     ct = np.cos(np.linspace(0, np.pi, 9))
     L = mie.default_lmax(k)
@@ -96,7 +96,7 @@ def test_sphere_spectra_S_and_D_by_quadrature(l):
 
 def test_pulsating_sphere_from_spectra():
     """Neumann data q = 1: (1/2 + D) u = (S + alpha M) q - alpha q / 2 on the
-    l = 0 mode gives the closed form u = 1/(1 - ik) (section 4.2)."""
+    l = 0 mode gives the closed form u = 1/(1 - ik) (section 5.2)."""
     for k in (2 * np.pi, 4 * np.pi, 3.3):
         s = mie.sphere_spectra(k, 0)
         a = 1j / k

@@ -1,7 +1,7 @@
 """Pins of the oracle's locally corrected Nystrom operator (section 2.2)
 against the analytic unit-sphere spectra of S, D, M, H (derived from the
 addition theorem, cross-checked by 2-D quadrature in test_oracle_mie) and the
-pulsating-sphere closed form (section 4.2).  Errors must fall with the mesh
+pulsating-sphere closed form (section 5.2).  Errors must fall with the mesh
 size at the rates a quadratic-geometry Nystrom method gives."""
 import numpy as np
 import pytest
@@ -41,7 +41,7 @@ def test_layer_operators_converge_to_sphere_spectra(l):
 def test_burton_miller_operators_and_pulsating_sphere():
     """BM_H = 1/2 + D + alpha H and BM_G = S + alpha M on the constant mode;
     q = 1 then gives u = (BM_G q - alpha q / 2) / BM_H -> 1/(1 - ik)."""
-    k = 2 * np.pi  # a characteristic frequency of the unit sphere (section 4.2)
+    k = 2 * np.pi  # a characteristic frequency of the unit sphere (section 5.2)
     el = synth.octa_sphere(8)
     n = 6 * el.shape[0]
     rows = np.arange(0, n, 61)
