@@ -46,21 +46,51 @@ WORKLOADS = {
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
-P2P_FLOPS_PER_PAIR = 67
+# FP64 operations of one H-kernel pair in the P2P kernel, counted from its
+# source with a fused multiply-add as two: position differences 3, r^2 5,
+# r and kr 2, sin and cos of kr 40 (reduction 7, two Horner polynomials 33),
+# G 3, the two normal projections and n_x.n_y 17, the kernel combination 26,
+# density product and accumulation 8, plus one reciprocal square root
+P2P_FLOPS_PER_PAIR = 110
+# one kernel evaluation at a check point in S2M (E_up = dG/dn_y) or L2T
+# (E_dn = G + alpha dG/dn_x), counted the same way: r and 1/r 8, sin and cos
+# 40, G and the normal factor about 20, accumulation 8
+EVAL_FLOPS = 76
 
 
 def m2l_work(plan_stats: dict) -> tuple[float, float]:
     """Algorithmic FP64 flops and HBM bytes of the M2L phase of one mat-vec:
     a dense compressed operator costs 8 s^2 real flops per pair, a rank-r
-    factorised one 16 r s; bytes count each unique operator once, each source
-    slot read per pair and each target slot read and written once."""
-    flops = 0.0
-    byts = 0.0
-    for L in plan_stats["levels"]:
-        s = L["s"]
-        flops += L.get("m2l_flops", 8.0 * s * s * L["m2l_pairs"])
-        byts += L.get("m2l_op_bytes", 0) + 16.0 * s * L["m2l_pairs"] + 32.0 * s * L["in_slots"]
+    factorised one 16 r s; the minimum bytes count each unique operator, each
+    source slot and each target slot once."""
+    flops = sum(L["m2l_flops"] for L in plan_stats["levels"])
+    byts = sum(L["m2l_min_bytes"] for L in plan_stats["levels"])
     return flops, byts
+
+
+def phase_rooflines(st: dict, phases: dict) -> dict:
+    """Achieved rates of the other far-field phases against the peak that
+    bounds them: M2M and L2L stream slots and small dense operators (HBM,
+    minimum bytes: unique operators, input and output slots once); S2M and
+    L2T evaluate kernels between leaf points and check points and apply W
+    (FP64 vector ALU)."""
+    out = {}
+    for name in ("m2m", "l2l"):
+        byts = sum(L[f"{name}_min_bytes"] for L in st["levels"])
+        flops = sum(L[f"{name}_flops"] for L in st["levels"])
+        ms = phases[name]
+        gbs = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        out[name] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": gbs / PEAK_HBM_GBS, "algorithmic_bytes": byts, "flops": flops,
+                     "tflops": flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0}
+    for name in ("s2m", "l2t"):
+        flops = EVAL_FLOPS * st[f"{name}_evals"] + st[f"{name}_w_flops"]
+        ms = phases[name]
+        tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        out[name] = {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tf / PEAK_FP64_TFLOPS, "kernel_evals": st[f"{name}_evals"],
+                     "flops_per_eval": EVAL_FLOPS, "w_flops": st[f"{name}_w_flops"]}
+    return out
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bm_h_matvec_sphere_N4009008_k500.md")
@@ -389,11 +419,19 @@ def main() -> int:
     for _ in range(args.warmup):
         plan.matvec(u, op, out=out)
     torch.cuda.synchronize()
+    # every step bracketed by HIP events on the stream the library launches on
+    # (torch's current stream); the whole run by the host clock
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for e0, e1 in evs:
+        e0.record()
         plan.matvec(u, op, out=out)
+        e1.record()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    step_ms = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    ms_median = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else 0.5 * (
+        step_ms[len(step_ms) // 2 - 1] + step_ms[len(step_ms) // 2])
     # per-phase HIP-event times over a second pass of the same steps
     plan.set_timing(True)
     for _ in range(args.steps):
@@ -410,10 +448,15 @@ def main() -> int:
         plan.matvec(u, op, out=out32, fp32=True)
     torch.cuda.synchronize()
     dt32 = time.perf_counter() - t0
+    # the FP32 error on the uncorrected H sum, where no FP64 term dilutes it
+    raw64 = plan.matvec(u, "RAW_H")
+    raw32 = plan.matvec(u, "RAW_H", fp32=True)
     fp32 = {"matvec_per_s": args.steps / dt32,
-            "rel_l2_vs_fp64": (torch.linalg.norm(out32 - out) / torch.linalg.norm(out)).item()}
+            "rel_l2_vs_fp64": (torch.linalg.norm(out32 - out) / torch.linalg.norm(out)).item(),
+            "raw_h_rel_l2_vs_fp64": (torch.linalg.norm(raw32 - raw64) / torch.linalg.norm(raw64)).item()}
+    del raw64, raw32
     print(f"[bench] FP32 mat-vec {fp32}", file=sys.stderr, flush=True)
-    ms = 1e3 * dt / args.steps
+    ms = ms_median
     free, total = torch.cuda.mem_get_info()
     peak_used = total - free
     flops, byts = m2l_work(st)
@@ -433,8 +476,7 @@ def main() -> int:
         "algorithmic_bytes_per_matvec": byts,
     }
     roof["frac"] = roof["achieved"] / roof["peak"]
-    # P2P against the FP64 vector peak: 67 flops per pair for the H kernel
-    # (distance, rsqrt, sin and cos each counted once, kernel and accumulation)
+    # P2P against the FP64 vector peak (operation count per pair above)
     p2p_flops = P2P_FLOPS_PER_PAIR * st["p2p_pairs"]
     p2p_roof = {"bound": "valu", "kernel": "P2P (near-field point sums)",
                 "achieved": p2p_flops / (phases["p2p"] * 1e-3) / 1e12 if phases["p2p"] > 0 else 0.0,
@@ -450,6 +492,8 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_mean": 1e3 * dt / args.steps,
+        "ms_per_step_min_max": [step_ms[0], step_ms[-1]],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -461,6 +505,7 @@ def main() -> int:
         "build_s": t_build,
         "roofline": roof,
         "p2p_roofline": p2p_roof,
+        "phase_rooflines": phase_rooflines(st, phases),
         "fp32": fp32,
     }
     if not args.no_solve and op == "BM_H":

@@ -158,6 +158,17 @@ int bm_solve(fda_plan *plan, int op, const void *rhs_dev, double tol, int maxit,
  * b_i = u_inc(x_i) + alpha du_inc/dn_x(x_i).  rhs_dev: complex128[N]. */
 int fda_rhs_plane_wave(fda_plan *plan, const double d[3], void *rhs_dev, void *hip_stream);
 
+/* Right-hand side of a Neumann problem without incident wave, e.g. the
+ * radiation of a vibrating body (section 2.1, eq. eq_bm with u_inc = 0;
+ * section 5.2): rhs = (S + alpha M) q - alpha c q with c = 1/2, where the
+ * layer operators carry the local corrections (the FDA_OP_BM_G operator of
+ * this plan) and alpha = i coupling / k.  q_dev: the normal derivative
+ * du/dn (normal into the body), rhs_dev: output; both complex128[N] device
+ * buffers in caller order that must not overlap.  Needs a plan built with
+ * elements and corrections & 2 (FDA_EINVAL otherwise).  Solve with
+ * bm_solve(FDA_OP_BM_H, rhs) for u on the surface.  Stream-ordered. */
+int fda_rhs_neumann(fda_plan *plan, const void *q_dev, void *rhs_dev, void *hip_stream);
+
 /* JSON description of the plan (levels, slot counts, ranks, memory, set-up
  * and per-phase timings of the last timed mat-vec).  Writes at most len bytes
  * including the terminating zero; returns FDA_EINVAL if it does not fit. */
@@ -175,11 +186,12 @@ int fda_phase_times(fda_plan *plan, double *ms, int n);
 
 /* ---- captured mat-vecs and batches of plans ----------------------------
  * Not steps of the paper's method: ways of launching it.  With graphs on, a
- * plan captures each (operator, input, output) mat-vec into a HIP graph the
- * first time and replays it afterwards (bm_solve steps use fixed internal
- * buffers, so one graph serves a whole solve); at most 8 graphs are kept per
- * plan.  Results are bitwise those of fda_matvec.  Graphs are bypassed while
- * fda_set_timing is on. */
+ * plan captures each (operator, input, output) mat-vec of fda_matvec and of
+ * bm_solve into a HIP graph the first time and replays it afterwards
+ * (bm_solve steps use fixed internal buffers, so one graph serves a whole
+ * solve); at most 8 graphs are kept per plan (fda_stats: graphs_captured),
+ * and turning graphs off releases them.  Results are bitwise those of the
+ * eager launches.  Graphs are bypassed while fda_set_timing is on. */
 int fda_set_graph(fda_plan *plan, int on);
 
 /* A batch groups plans on the current device (each plan at most once; the

@@ -161,21 +161,30 @@ int fda_build(const fda_geometry *g, double k, double eps, const fda_opts *o, fd
     });
 }
 
+// Operator code valid for this plan: a known base operator, no bits beyond
+// FDA_OP_FP32, an FP32 far field only on plans that hold one, and the
+// corrected operators only with their correction tables.
+static void check_op(const Plan &P, int op)
+{
+    const int base = op & 0xff;
+    if (base < FDA_OP_RAW_H || base > FDA_OP_BM_G || (op & ~0x1ff)) throw std::invalid_argument("unknown operator");
+    if ((op & FDA_OP_FP32) && P.opt.precision == FDA_PREC_FP64)
+        throw std::invalid_argument("FP32 operator requested on an FP64-only plan");
+    if (base == FDA_OP_BM_H && !P.has_corr)
+        throw std::invalid_argument("the corrected H operator needs a plan built with elements");
+    if (base == FDA_OP_BM_G && !P.has_corr_g)
+        throw std::invalid_argument("the corrected G operator needs a plan built with elements and corrections & 2");
+}
+
 int fda_matvec(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *stream)
 {
     return guarded([&] {
         if (!plan || !in_dev || !out_dev) throw std::invalid_argument("null argument");
-        const int base = op & 0xff;
-        if (base < FDA_OP_RAW_H || base > FDA_OP_BM_G || (op & ~0x1ff)) throw std::invalid_argument("unknown operator");
         if (in_dev == out_dev) throw std::invalid_argument("input and output must not alias");
         Plan &P = *plan->P;
-        if ((op & FDA_OP_FP32) && P.opt.precision == FDA_PREC_FP64)
-            throw std::invalid_argument("FP32 operator requested on an FP64-only plan");
-        if (base == FDA_OP_BM_H && !P.has_corr)
-            throw std::invalid_argument("the corrected H operator needs a plan built with elements");
-        if (base == FDA_OP_BM_G && !P.has_corr_g)
-            throw std::invalid_argument("the corrected G operator needs a plan built with elements and corrections & 2");
-        device_matvec(P, op, (const double2 *)in_dev, (double2 *)out_dev, (hipStream_t)stream);
+        check_op(P, op);
+        // replays a captured graph when the plan has graphs on (fda_set_graph)
+        graph_matvec(P, op, (const double2 *)in_dev, (double2 *)out_dev, (hipStream_t)stream);
         return FDA_OK;
     });
 }
@@ -186,13 +195,9 @@ int bm_solve(fda_plan *plan, int op, const void *rhs_dev, double tol, int maxit,
     return guarded([&] {
         if (!plan || !rhs_dev || !x_dev) throw std::invalid_argument("null argument");
         if (!(tol > 0) || maxit < 1 || restart < 1) throw std::invalid_argument("bad solver parameters");
-        const int base = op & 0xff;
-        if (base < FDA_OP_RAW_H || base > FDA_OP_BM_G || (op & ~0x1ff)) throw std::invalid_argument("unknown operator");
+        if (precond < 0 || precond > 3) throw std::invalid_argument("unknown preconditioner");
         Plan &P = *plan->P;
-        if ((op & FDA_OP_FP32) && P.opt.precision == FDA_PREC_FP64)
-            throw std::invalid_argument("FP32 operator requested on an FP64-only plan");
-        if ((base == FDA_OP_BM_H && !P.has_corr) || (base == FDA_OP_BM_G && !P.has_corr_g))
-            throw std::invalid_argument("corrected operators need a plan built with elements");
+        check_op(P, op);
         const int rc = device_gmres(P, op, (const double2 *)rhs_dev, tol, maxit, restart, precond, (double2 *)x_dev,
                                     iters_out, relres_out, resid_hist, (hipStream_t)stream);
         if (rc == FDA_NOT_CONVERGED) return fail(rc, "GMRES did not reach the tolerance");
@@ -212,6 +217,19 @@ int fda_rhs_plane_wave(fda_plan *plan, const double d[3], void *rhs_dev, void *s
         const double s = 1.0 / std::sqrt(n2);
         const double dd[3] = {d[0] * s, d[1] * s, d[2] * s};
         device_rhs_plane_wave(*plan->P, dd, (double2 *)rhs_dev, (hipStream_t)stream);
+        return FDA_OK;
+    });
+}
+
+int fda_rhs_neumann(fda_plan *plan, const void *q_dev, void *rhs_dev, void *stream)
+{
+    return guarded([&] {
+        if (!plan || !q_dev || !rhs_dev) throw std::invalid_argument("null argument");
+        if (q_dev == rhs_dev) throw std::invalid_argument("q and rhs must not alias");
+        Plan &P = *plan->P;
+        if (!P.has_corr_g)
+            throw std::invalid_argument("the Neumann right-hand side needs a plan built with elements and corrections & 2");
+        device_rhs_neumann(P, (const double2 *)q_dev, (double2 *)rhs_dev, (hipStream_t)stream);
         return FDA_OK;
     });
 }
@@ -246,6 +264,7 @@ int fda_stats(const fda_plan *plan, char *buf, size_t len)
                 }
                 s += "]";
             }
+            s += ", \"graphs_captured\": " + std::to_string(P.dev->graphs.size());
             s += ", \"m2l_mode\": " + std::to_string(P.dev->m2l_mode) + ", \"m2l_tile\": " + std::to_string(tile) +
                  ", \"m2l_chunk\": " + std::to_string(chunk) + ", \"m2l_lds_bytes\": " + std::to_string(shm) +
                  ", \"max_lds_per_block\": " + std::to_string(maxsh) + ", \"m2l_tiles\": [";
@@ -314,14 +333,11 @@ int fda_batch_matvec(fda_batch *b, int op, const void *const *in_dev, void *cons
 {
     return guarded([&] {
         if (!b || !in_dev || !out_dev) throw std::invalid_argument("null argument");
-        const int base = op & 0xff;
-        if (base < FDA_OP_RAW_H || base > FDA_OP_BM_G || (op & ~0x1ff)) throw std::invalid_argument("unknown op");
         for (size_t i = 0; i < b->plans.size(); ++i) {
             const Plan &P = *b->plans[i]->P;
             if (!in_dev[i] || !out_dev[i]) throw std::invalid_argument("null vector in batch");
-            if ((op & FDA_OP_FP32) && P.opt.precision == FDA_PREC_FP64)
-                throw std::invalid_argument("FP32 operator requested on an FP64-only plan");
-            if (base >= FDA_OP_BM_H && !P.has_corr) throw std::invalid_argument("BM operator needs elements");
+            if (in_dev[i] == out_dev[i]) throw std::invalid_argument("input and output must not alias");
+            check_op(P, op);
         }
         batch_matvec(b->B, op, (const double2 *const *)in_dev, (double2 *const *)out_dev, (hipStream_t)stream);
         return FDA_OK;
@@ -334,11 +350,11 @@ int fda_batch_solve(fda_batch *b, int op, const void *const *rhs_dev, double tol
     return guarded([&] {
         if (!b || !rhs_dev || !x_dev || !status) throw std::invalid_argument("null argument");
         if (!(tol > 0) || maxit <= 0 || restart <= 0) throw std::invalid_argument("bad GMRES parameters");
+        if (precond < 0 || precond > 3) throw std::invalid_argument("unknown preconditioner");
         for (size_t i = 0; i < b->plans.size(); ++i) {
             const Plan &P = *b->plans[i]->P;
             if (!rhs_dev[i] || !x_dev[i]) throw std::invalid_argument("null vector in batch");
-            if ((op & FDA_OP_FP32) && P.opt.precision == FDA_PREC_FP64)
-                throw std::invalid_argument("FP32 operator requested on an FP64-only plan");
+            check_op(P, op);
             if (precond && !P.has_corr) throw std::invalid_argument("preconditioner needs elements");
         }
         const int bad = batch_solve(b->B, op, (const double2 *const *)rhs_dev, tol, maxit, restart, precond,

@@ -14,6 +14,9 @@
 //   un-permute, free term, near-field correction SpMV (caller order)
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -1030,6 +1033,20 @@ __global__ void k_plane_wave(const double *__restrict__ X, const double *__restr
     rhs[perm[i]] = make_double2(cs * f, sn * f);
 }
 
+// Neumann data on the right-hand side: rhs_i -= a q_i with a = alpha c the
+// jump term of the adjoint operator (c = 1/2 on a smooth surface).
+__global__ void k_sub_scaled(const double2 *__restrict__ q, double a_re, double a_im, double2 *__restrict__ rhs,
+                             int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 v = q[i];
+    double2 r = rhs[i];
+    r.x -= a_re * v.x - a_im * v.y;
+    r.y -= a_re * v.y + a_im * v.x;
+    rhs[i] = r;
+}
+
 // ---------------------------------------------------------------- host side
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -1179,10 +1196,18 @@ static void free_chunks(Device &D, DChunks &c)
 }
 
 // Dynamic LDS limit of every matrix-core chunk kernel instance, raised to at
-// least `bytes` (the default limit is 64 KiB).
+// least `bytes` (the default limit is 64 KiB).  The attribute belongs to the
+// kernel on the device, not to a plan, so the limit reached on each device is
+// kept process-wide and only ever raised: a later plan with smaller chunks
+// must not lower it below what an earlier plan's launches need.
 static void set_mfma_lds(Device &D, size_t bytes)
 {
-    if (bytes <= 65536 || bytes <= D.mfma_lds) return;
+    static std::mutex mu;
+    static std::map<int, size_t> reached;  // device -> limit set so far
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &have = reached[D.device];
+    D.mfma_lds = std::max(D.mfma_lds, have);
+    if (bytes <= 65536 || bytes <= have) return;
     for (const void *f : {(const void *)k_chunks_mfma<double, false, 1, TAG_M2L>,
                           (const void *)k_chunks_mfma<double, false, 1, TAG_M2M>,
                           (const void *)k_chunks_mfma<double, true, 1, TAG_L2L>,
@@ -1196,6 +1221,7 @@ static void set_mfma_lds(Device &D, size_t bytes)
                           (const void *)k_chunks_mfma<float, false, 2, TAG_M2M>,
                           (const void *)k_chunks_mfma<float, true, 2, TAG_L2L>})
         HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    have = bytes;
     D.mfma_lds = bytes;
 }
 
@@ -1654,7 +1680,7 @@ static void launch_l2t(Plan &P, Device &D, const O &c, const typename Cx<R>::T *
 template <typename R, typename O>
 static void far_field_chunks(Plan &P, Device &D, const O &c, const typename Cx<R>::T *mat, const typename Cx<R>::T *tW,
                              const typename Cx<R>::T *tWt, typename Cx<R>::T *od, typename Cx<R>::T *id,
-                             hipEvent_t *ev, hipStream_t st)
+                             void *part, hipEvent_t *ev, hipStream_t st)
 {
     using C = typename Cx<R>::T;
     if (D.n_od) hipLaunchKernelGGL(k_fill_zero<C>, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, od, D.n_od);
@@ -1664,21 +1690,21 @@ static void far_field_chunks(Plan &P, Device &D, const O &c, const typename Cx<R
     const bool slabs = D.m2l_mode == 3;
     for (int l = D.n_lev - 2; l >= 0; --l) {
         if (slabs)
-            launch_slabs<TAG_M2M, false, R>(D.m2ms[l], D.part, mat, od, od, st);
+            launch_slabs<TAG_M2M, false, R>(D.m2ms[l], part, mat, od, od, st);
         else
             launch_chunks<TAG_M2M, false, R>(D.m2mc[l], D.m2mc[l].cols, mat, od, od, st);
     }
     if (ev) HIP_CHECK(hipEventRecord(ev[4], st));
     for (int l = 0; l < D.n_lev; ++l) {
         if (slabs)
-            launch_slabs<TAG_M2L, false, R>(D.m2ls[l], D.part, mat, od, id, st);
+            launch_slabs<TAG_M2L, false, R>(D.m2ls[l], part, mat, od, id, st);
         else
             launch_chunks<TAG_M2L, false, R>(D.m2lc[l], D.m2lc[l].s, mat, od, id, st);
     }
     if (ev) HIP_CHECK(hipEventRecord(ev[5], st));
     for (int l = 1; l < D.n_lev; ++l) {
         if (slabs)
-            launch_slabs<TAG_L2L, true, R>(D.l2ls[l], D.part, mat, id, id, st);
+            launch_slabs<TAG_L2L, true, R>(D.l2ls[l], part, mat, id, id, st);
         else
             launch_chunks<TAG_L2L, true, R>(D.l2lc[l], D.l2lc[l].cols, mat, id, id, st);
     }
@@ -1686,9 +1712,10 @@ static void far_field_chunks(Plan &P, Device &D, const O &c, const typename Cx<R
     launch_l2t<R, O>(P, D, c, tWt, id, st);
 }
 
-void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st)
+void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st, void *part)
 {
     Device &D = *P.dev;
+    if (!part) part = D.part;
     const int64_t N = P.N;
     // low byte: operator; FDA_OP_FP32 (0x100) selects the FP32 far field and
     // near field on plans built with both precisions
@@ -1708,9 +1735,9 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
     if (P.opt.far_field && f32) {
         const OpCf cf = {make_float2((float)c.c0.x, (float)c.c0.y), make_float2((float)c.c1.x, (float)c.c1.y),
                          make_float2((float)c.d0.x, (float)c.d0.y), make_float2((float)c.d1.x, (float)c.d1.y)};
-        far_field_chunks<float, OpCf>(P, D, cf, D.matf, D.t_Wf, D.t_Wtf, D.odf, D.idf, ev, st);
+        far_field_chunks<float, OpCf>(P, D, cf, D.matf, D.t_Wf, D.t_Wtf, D.odf, D.idf, part, ev, st);
     } else if (P.opt.far_field && (D.m2l_mode == 0 || D.m2l_mode == 3)) {
-        far_field_chunks<double, OpC>(P, D, c, D.mat, D.t_W, D.t_Wt, D.od, D.id, ev, st);
+        far_field_chunks<double, OpC>(P, D, c, D.mat, D.t_W, D.t_Wt, D.od, D.id, part, ev, st);
     } else if (P.opt.far_field) {
         if (D.n_od) hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, D.od, D.n_od);
         if (D.n_id) hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_id, 256)), dim3(256), 0, st, D.id, D.n_id);
@@ -1787,6 +1814,17 @@ void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t
     Device &D = *P.dev;
     hipLaunchKernelGGL(k_plane_wave, dim3(nblk(P.N, 256)), dim3(256), 0, st, D.x, D.y, D.z, D.nx, D.ny, D.nz, D.perm,
                        P.k, P.opt.coupling, d[0], d[1], d[2], rhs, P.N);
+    HIP_CHECK(hipGetLastError());
+}
+
+// Right-hand side of a Neumann (radiation) problem: (S + alpha M) q through
+// the corrected G operator, minus alpha c q with c = 1/2.
+void device_rhs_neumann(Plan &P, const double2 *q, double2 *rhs, hipStream_t st)
+{
+    device_matvec(P, 4 /* FDA_OP_BM_G */, q, rhs, st);
+    // alpha = i coupling / k, so alpha / 2 = (0, coupling / (2 k))
+    hipLaunchKernelGGL(k_sub_scaled, dim3(nblk(P.N, 256)), dim3(256), 0, st, q, 0.0, 0.5 * P.opt.coupling / P.k, rhs,
+                       P.N);
     HIP_CHECK(hipGetLastError());
 }
 

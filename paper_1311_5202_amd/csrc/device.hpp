@@ -166,7 +166,8 @@ void learned_detach(Plan &P);
 double learned_loss_grad_raw(LearnedNet *N, int nb, const int64_t *poff, const int *bsize, const int *bne,
                              const int64_t *boff, const int64_t *toff, int64_t n_rows, const double *F,
                              const double2 *Binv, const double2 *T);
-void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st);
+void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st, void *part = nullptr);
+
 // device_matvec through a captured graph when the plan has graphs enabled
 void graph_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st);
 void graph_release(Device &D);
@@ -178,6 +179,7 @@ void batch_matvec(Batch *B, int op, const double2 *const *in, double2 *const *ou
 int batch_solve(Batch *B, int op, const double2 *const *rhs, double tol, int maxit, int restart, int precond,
                 double2 *const *x, int *iters, double *relres, int *status);
 void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t st);
+void device_rhs_neumann(Plan &P, const double2 *q, double2 *rhs, hipStream_t st);
 int device_gmres(Plan &P, int op, const double2 *b, double tol, int maxit, int restart, int precond, double2 *x,
                  int *iters, double *relres, double *hist, hipStream_t st);
 

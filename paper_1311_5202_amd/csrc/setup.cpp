@@ -110,15 +110,64 @@ std::string plan_stats(const Plan &P)
                     opbytes += 16.0 * (r >= 0 ? (double)r * (G.rows + G.cols) : (double)G.rows * G.cols);
             }
         }
+        // M2M (child slots of level l+1 -> parent slots of level l) and L2L
+        // (parent slots of level l-1 -> child slots of level l): flops of the
+        // dense compressed operators, and the minimum bytes: each unique
+        // operator, each input slot and each output slot once
+        auto list_work = [](const GemvList &G, double &fl, double &by, int64_t &ent) {
+            std::unordered_map<int64_t, int> ops;
+            std::unordered_map<int64_t, int> ins;
+            fl = 0;
+            by = 0;
+            ent = (int64_t)G.in_off.size();
+            for (size_t q = 0; q < G.in_off.size(); ++q) {
+                const int r = G.rank[q];
+                fl += r >= 0 ? 8.0 * r * (G.rows + G.cols) : 8.0 * G.rows * G.cols;
+                if (ops.emplace(G.mat_off[q], 1).second)
+                    by += 16.0 * (r >= 0 ? (double)r * (G.rows + G.cols) : (double)G.rows * G.cols);
+                if (ins.emplace(G.in_off[q], 1).second) by += 16.0 * G.cols;
+            }
+            by += 16.0 * G.rows * (double)G.out_off.size();
+        };
+        double m2m_fl = 0, m2m_by = 0, l2l_fl = 0, l2l_by = 0, m2l_min = 0;
+        int64_t m2m_e = 0, l2l_e = 0;
+        if (l < P.m2m_lists.size()) list_work(P.m2m_lists[l], m2m_fl, m2m_by, m2m_e);
+        if (l < P.l2l_lists.size()) list_work(P.l2l_lists[l], l2l_fl, l2l_by, l2l_e);
+        if (l < P.m2l_lists.size()) {
+            double fl;
+            int64_t e;
+            list_work(P.m2l_lists[l], fl, m2l_min, e);
+        }
         o << (l ? ", " : "") << "{\"w\": " << L.w << ", \"hf\": " << (L.hf ? 1 : 0) << ", \"m\": " << L.m
           << ", \"cubes\": " << L.cubes.size() << ", \"out_slots\": " << L.n_out << ", \"in_slots\": " << L.n_in
           << ", \"s\": " << (l < P.tmpl.size() ? P.tmpl[l].s : 0)
           << ", \"n_equiv\": " << (l < P.tmpl.size() ? P.tmpl[l].X.size() / 3 : 0)
           << ", \"n_check\": " << (l < P.tmpl.size() ? P.tmpl[l].Y.size() / 3 : 0) << ", \"m2l_pairs\": " << npairs
           << ", \"m2l_ops\": " << nk << ", \"m2l_pairs_lowrank\": " << nlr << ", \"m2l_flops\": " << flops
-          << ", \"m2l_op_bytes\": " << opbytes << "}";
+          << ", \"m2l_op_bytes\": " << opbytes << ", \"m2l_min_bytes\": " << m2l_min
+          << ", \"m2m_entries\": " << m2m_e << ", \"m2m_flops\": " << m2m_fl << ", \"m2m_min_bytes\": " << m2m_by
+          << ", \"l2l_entries\": " << l2l_e << ", \"l2l_flops\": " << l2l_fl << ", \"l2l_min_bytes\": " << l2l_by
+          << "}";
     }
-    o << "]}";
+    o << "]";
+    // S2M and L2T: kernel evaluations between leaf points and the level's
+    // check points, and the complex multiply-adds of W (s x |Y|) per leaf
+    auto leaf_work = [&](const std::vector<LeafTask> &T, double &ev, double &wf) {
+        ev = 0;
+        wf = 0;
+        for (const LeafTask &t : T) {
+            const LevelTemplate &L = P.tmpl[t.tmpl];
+            const double ny = (double)(L.Y.size() / 3);
+            ev += (double)(t.end - t.start) * ny;
+            wf += 8.0 * L.s * ny;
+        }
+    };
+    double s2m_ev, s2m_wf, l2t_ev, l2t_wf;
+    leaf_work(P.s2m_tasks, s2m_ev, s2m_wf);
+    leaf_work(P.l2t_tasks, l2t_ev, l2t_wf);
+    o << ", \"s2m_evals\": " << s2m_ev << ", \"s2m_w_flops\": " << s2m_wf << ", \"l2t_evals\": " << l2t_ev
+      << ", \"l2t_w_flops\": " << l2t_wf << ", \"n_s2m_tasks\": " << P.s2m_tasks.size()
+      << ", \"n_l2t_tasks\": " << P.l2t_tasks.size() << "}";
     return o.str();
 }
 

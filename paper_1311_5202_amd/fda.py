@@ -121,6 +121,17 @@ class Plan:
         _abi.check(_abi.lib().fda_rhs_plane_wave(self._h, dd, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
+    def rhs_neumann(self, q, stream=None):
+        """(S + alpha M) q - alpha q / 2 with the corrected operators
+        (fda_rhs_neumann): the right-hand side of a radiation problem."""
+        import torch
+
+        _check_vec(q, self.n)
+        out = torch.empty_like(q)
+        _abi.check(_abi.lib().fda_rhs_neumann(self._h, ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                              _stream_ptr(stream)))
+        return out
+
     def solve(self, rhs, tol: float, maxit: int = 200, restart: int = 200, op: str = "BM_H", precond: int = 0,
               stream=None, raise_on_fail: bool = True, fp32: bool = False):
         import torch

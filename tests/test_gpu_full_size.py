@@ -2,9 +2,7 @@
 kD = 1000), in the configuration bench.py times: sampled rows of the raw H
 sum (FP64 and FP32) and of the corrected BM_H operator against the oracle,
 and the plane-wave solve against the Mie series.  The plan build takes
-minutes, so the test runs only with FDBEM_FULL=1."""
-import os
-
+two to three minutes."""
 import numpy as np
 import pytest
 
@@ -12,10 +10,10 @@ import oracle
 import synth
 from oracle import mie, near
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skipif(os.environ.get("FDBEM_FULL") != "1",
-                                                  reason="full-size build takes minutes; set FDBEM_FULL=1")]
+pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.timeout(900)
 def test_full_size_sampled_rows_and_mie():
     import torch
 

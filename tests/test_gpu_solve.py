@@ -81,7 +81,10 @@ def test_pulsating_sphere_at_characteristic_frequency(torch):
     k = 2 * np.pi
     el, pts, nrm, w, plan = _plan(8, k, corrections=3)
     q = torch.ones(len(w), dtype=torch.complex128, device="cuda")
-    rhs = plan.matvec(q, "BM_G") - 0.5 * (1j / k) * q
+    rhs = plan.rhs_neumann(q)
+    # the entry point is the corrected G operator minus the jump term alpha q / 2
+    ref = plan.matvec(q, "BM_G") - 0.5 * (1j / k) * q
+    assert torch.allclose(rhs, ref, rtol=1e-14, atol=1e-14)
     x, info = plan.solve(rhs, 1e-8, maxit=100, restart=100)
     u_ref = mie.pulsating_sphere(k)
     err = np.max(np.abs(x.cpu().numpy() - u_ref)) / abs(u_ref)
