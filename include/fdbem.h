@@ -141,6 +141,19 @@ int fda_build(const fda_geometry *geom, double k, double eps, const fda_opts *op
  * built with elements.  Stream-ordered, no synchronisation. */
 int fda_matvec(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *hip_stream);
 
+/* fda_matvec that allocates nothing, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same operators, arguments and
+ * result as fda_matvec (never through a captured graph).  The per-pair
+ * translation results that fda_matvec keeps in the plan's slab buffer go to
+ * a static 256 MiB device array of the library instead; each device holds
+ * its own copy until the process ends, and every call on that device shares
+ * it, so calls that overlap on one device race (order them on one stream).
+ * FDA_EINVAL if the plan's largest slab needs more than 256 MiB (build it
+ * with slab_mb <= 256), if it uses a schedule other than the operator
+ * chunks (m2l_tile 0 or 1), or if the plan's device is not current. */
+int fda_matvec_noalloc(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *hip_stream);
+
 /* Solve Op x = rhs by GMRES (section 2.2 eq. Axb; right preconditioned,
  * x0 = 0, restart length `restart`, Arnoldi by classical Gram-Schmidt with
  * re-orthogonalisation, FP64).  Stops when ||b - A x|| / ||b|| <= tol.

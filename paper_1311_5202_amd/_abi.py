@@ -25,7 +25,7 @@ EXPORTS = ("fda_default_opts", "bem_nystrom_nodes", "bem_near_correction", "fda_
            "fda_stats", "fda_set_timing", "fda_phase_times", "fda_destroy", "fda_last_error", "fda_net_num_params",
            "fda_net_create", "fda_net_destroy", "fda_net_get_params", "fda_net_set_params", "fda_net_loss_grad",
            "fda_net_train_step", "fda_net_attach", "fda_net_loss_grad_raw", "fda_set_graph", "fda_batch_create",
-           "fda_batch_matvec", "fda_batch_solve", "fda_batch_destroy", "fda_rhs_neumann")
+           "fda_batch_matvec", "fda_batch_solve", "fda_batch_destroy", "fda_rhs_neumann", "fda_matvec_noalloc")
 
 
 class FdaGeometry(ctypes.Structure):

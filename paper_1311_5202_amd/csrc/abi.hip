@@ -189,6 +189,21 @@ int fda_matvec(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *
     });
 }
 
+int fda_matvec_noalloc(fda_plan *plan, int op, const void *in_dev, void *out_dev, void *stream)
+{
+    return guarded([&] {
+        if (!plan || !in_dev || !out_dev) throw std::invalid_argument("null argument");
+        if (in_dev == out_dev) throw std::invalid_argument("input and output must not alias");
+        Plan &P = *plan->P;
+        check_op(P, op);
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != P.dev->device)
+            throw std::invalid_argument("the plan's device is not the current device");
+        device_matvec_static(P, op, (const double2 *)in_dev, (double2 *)out_dev, (hipStream_t)stream);
+        return FDA_OK;
+    });
+}
+
 int bm_solve(fda_plan *plan, int op, const void *rhs_dev, double tol, int maxit, int restart, int precond,
              void *x_dev, int *iters_out, double *relres_out, double *resid_hist, void *stream)
 {

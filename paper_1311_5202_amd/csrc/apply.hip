@@ -1307,6 +1307,7 @@ void device_upload(Plan &P)
     P.dev = Dp;
     Device &D = *Dp;
     HIP_CHECK(hipGetDevice(&D.device));
+    D.static_part = static_scratch_address(D.device);
     D.x = dupload(D, P.px);
     D.y = dupload(D, P.py);
     D.z = dupload(D, P.pz);
@@ -1815,6 +1816,48 @@ void device_rhs_plane_wave(Plan &P, const double d[3], double2 *rhs, hipStream_t
     hipLaunchKernelGGL(k_plane_wave, dim3(nblk(P.N, 256)), dim3(256), 0, st, D.x, D.y, D.z, D.nx, D.ny, D.nz, D.perm,
                        P.k, P.opt.coupling, d[0], d[1], d[2], rhs, P.N);
     HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- static scratch
+// Per-pair translation results of the allocation-free mat-vec live in this
+// file-scope device array instead of the plan's slab buffer.  Each device the
+// library runs on holds its own copy for the life of the process.  In host
+// code the name is only a stand-in: the device address comes from
+// hipGetSymbolAddress, looked up once per device at plan set-up.
+static __device__ __align__(256) double2 scratch[kStaticScratchBytes / sizeof(double2)];
+
+void *static_scratch_address(int device)
+{
+    static std::mutex mu;
+    static std::map<int, void *> addr;  // device -> address of its copy
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) return it->second;
+    int cur = -1;
+    HIP_CHECK(hipGetDevice(&cur));
+    if (cur != device) throw std::runtime_error("static scratch looked up with another device current");
+    void *p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw std::runtime_error("no device address for the static scratch");
+    addr[device] = p;
+    return p;
+}
+
+// The mat-vec of device_matvec with the per-pair results in the static
+// scratch.  Everything it reads or writes besides the vectors was allocated
+// when the plan was built; the scratch rows are written before they are read,
+// so nothing has to be cleared.
+void device_matvec_static(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st)
+{
+    Device &D = *P.dev;
+    if (D.m2l_mode != 3 && D.m2l_mode != 0)
+        throw std::invalid_argument("the allocation-free mat-vec needs the operator-chunk translation schedule");
+    if (D.part_bytes > kStaticScratchBytes)
+        throw std::invalid_argument("the plan's translation slabs need " + std::to_string(D.part_bytes) +
+                                    " bytes of scratch, more than the static " + std::to_string(kStaticScratchBytes) +
+                                    " bytes: build it with slab_mb <= " + std::to_string(kStaticScratchBytes >> 20));
+    if (!D.static_part) throw std::runtime_error("static scratch address missing");
+    device_matvec(P, op, in, out, st, D.static_part);
 }
 
 // Right-hand side of a Neumann (radiation) problem: (S + alpha M) q through

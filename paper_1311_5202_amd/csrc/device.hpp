@@ -101,6 +101,7 @@ struct Device {
     std::vector<std::vector<DChunks>> m2ls, m2ms, l2ls;
     void *part = nullptr;
     size_t part_bytes = 0;
+    void *static_part = nullptr;       // this device's copy of the static scratch
     int m2l_mode = 0;                  // 0 operator chunks, 1 per-target GEMV, 2 target tiles
     double2 *m2l_part = nullptr;       // partial sums of split tiles
     std::vector<std::array<int64_t, 4>> tile_stats;  // per level: tiles, chunks, pairs, segments
@@ -167,7 +168,10 @@ double learned_loss_grad_raw(LearnedNet *N, int nb, const int64_t *poff, const i
                              const int64_t *boff, const int64_t *toff, int64_t n_rows, const double *F,
                              const double2 *Binv, const double2 *T);
 void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st, void *part = nullptr);
-
+// size of the file-scope scratch of the allocation-free mat-vec
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+void *static_scratch_address(int device);
+void device_matvec_static(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st);
 // device_matvec through a captured graph when the plan has graphs enabled
 void graph_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st);
 void graph_release(Device &D);

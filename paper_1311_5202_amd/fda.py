@@ -113,6 +113,19 @@ class Plan:
                                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
+    def matvec_noalloc(self, u, op: str = "RAW_H", out=None, stream=None, fp32: bool = False):
+        """fda_matvec_noalloc: the mat-vec with the library's static scratch
+        (out must be supplied by callers that may not allocate)."""
+        import torch
+
+        _check_vec(u, self.n)
+        if out is None:
+            out = torch.empty_like(u)
+        _check_vec(out, self.n)
+        _abi.check(_abi.lib().fda_matvec_noalloc(self._h, self._op(op, fp32), ctypes.c_void_p(u.data_ptr()),
+                                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
     def rhs_plane_wave(self, d, stream=None):
         import torch
 
