@@ -76,7 +76,10 @@ typedef struct {
 } fda_geometry;
 
 typedef struct {
-    double svd_eps;     /* truncation of the pseudo-inverses (eq. eq_invr); 0 -> eps      */
+    double svd_eps;     /* truncation of the pseudo-inverses (eq. eq_invr); 0 -> eps for the
+                           low-frequency templates and eps/3 for the high-frequency ones
+                           (fitted on a skeleton of the region the field is evaluated in,
+                           they err about three times the truncation between its points) */
     double lowrank_eps; /* truncation of the low-rank M2L factors (eq. eq_lrdk); 0 -> eps */
     int leaf_cap;       /* max points per octree leaf; 0 -> 64                            */
     int leaf_rule;      /* 0: leaves are low-frequency cubes (w < lambda)                  */
@@ -100,6 +103,11 @@ typedef struct {
                            chunk on the plan's own lists and keep the faster per translation
                            and level (fda_stats: m2l_/m2m_/l2l_autotune); 0: 16 */
     int slab_mb;        /* scratch for per-pair translation results, MiB per slab; 0 -> 1024 */
+    int hf_template;    /* high-frequency templates: 0 (default) one per wedge orbit, check
+                           points on the region where the wedge's outgoing field is evaluated
+                           (M2L target cubes, parent check points), equivalent points on the
+                           cube's surface; 1: the earlier circular check cone and ball of
+                           equivalent points rotated to each wedge (larger s)               */
 } fda_opts;
 
 typedef struct fda_plan fda_plan;
@@ -135,6 +143,14 @@ int bem_near_correction(int64_t n_elem, const double *elem, const double *pts, c
  * (0,1) the controlling accuracy.  opts may be NULL (defaults).  Host work
  * is FP64; everything the mat-vec reads is uploaded.  Synchronous. */
 int fda_build(const fda_geometry *geom, double k, double eps, const fda_opts *opts, fda_plan **out);
+
+/* The host part of fda_build without a device: octree and lists (section
+ * 3.1.1), templates (section 3.1.2, eqs. eq_svdr/eq_invr) and compressed
+ * operators (sections 4.1, 4.2), described as the JSON of fda_stats (levels,
+ * reduced dimensions s, pair and operator counts, work per phase).  For
+ * inspecting and sizing a plan on a machine without a GPU.  Writes at most
+ * len bytes including the terminating zero (FDA_EINVAL if it does not fit). */
+int fda_analyze(const fda_geometry *geom, double k, double eps, const fda_opts *opts, char *json_buf, size_t len);
 
 /* out_dev = Op(in_dev) for op in FDA_OP_*: both complex128[N] device
  * buffers in caller order (they must not overlap).  BM_* ops need a plan

@@ -7,4 +7,4 @@ raises if it is missing.
 """
 
 from ._abi import LIB_PATH, OPS, FdaError, lib  # noqa: F401
-from .fda import Batch, Net, Plan, build, near_correction, nystrom_nodes  # noqa: F401
+from .fda import Batch, Net, Plan, analyze, build, near_correction, nystrom_nodes  # noqa: F401

@@ -25,7 +25,7 @@ EXPORTS = ("fda_default_opts", "bem_nystrom_nodes", "bem_near_correction", "fda_
            "fda_stats", "fda_set_timing", "fda_phase_times", "fda_destroy", "fda_last_error", "fda_net_num_params",
            "fda_net_create", "fda_net_destroy", "fda_net_get_params", "fda_net_set_params", "fda_net_loss_grad",
            "fda_net_train_step", "fda_net_attach", "fda_net_loss_grad_raw", "fda_set_graph", "fda_batch_create",
-           "fda_batch_matvec", "fda_batch_solve", "fda_batch_destroy", "fda_rhs_neumann", "fda_matvec_noalloc")
+           "fda_batch_matvec", "fda_batch_solve", "fda_batch_destroy", "fda_rhs_neumann", "fda_matvec_noalloc", "fda_analyze")
 
 
 class FdaGeometry(ctypes.Structure):
@@ -41,7 +41,8 @@ class FdaOpts(ctypes.Structure):
                 ("p2p_threshold", ctypes.c_double),
                 ("coupling", ctypes.c_double),
                 ("autotune", ctypes.c_int),
-                ("slab_mb", ctypes.c_int)]
+                ("slab_mb", ctypes.c_int),
+                ("hf_template", ctypes.c_int)]
 
 
 class FdaError(RuntimeError):
@@ -88,6 +89,10 @@ def lib() -> ctypes.CDLL:
     L.fda_batch_solve.argtypes = [vp, ci, vp, dbl, ci, ci, ci, vp, vp, vp, vp]
     L.fda_batch_destroy.argtypes = [vp]
     L.fda_batch_destroy.restype = None
+    L.fda_rhs_neumann.argtypes = [vp, vp, vp, vp]
+    L.fda_matvec_noalloc.argtypes = [vp, ci, vp, vp, vp]
+    L.fda_analyze.argtypes = [ctypes.POINTER(FdaGeometry), dbl, dbl, ctypes.POINTER(FdaOpts), ctypes.c_char_p,
+                              ctypes.c_size_t]
     L.fda_destroy.argtypes = [vp]
     L.fda_destroy.restype = None
     L.fda_last_error.restype = ctypes.c_char_p

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -85,6 +86,7 @@ int fda_default_opts(fda_opts *o)
     o->coupling = 1.0;
     o->autotune = 1;
     o->slab_mb = 0;
+    o->hf_template = 0;
     return FDA_OK;
 }
 
@@ -119,34 +121,56 @@ int bem_near_correction(int64_t n_elem, const double *elem, const double *pts, c
     });
 }
 
+// Options of the C ABI in the internal form (NULL: defaults), validated.
+static Options parse_opts(const fda_opts *o)
+{
+    Options opt;
+    if (o) {
+        opt.svd_eps = o->svd_eps;
+        opt.lowrank_eps = o->lowrank_eps;
+        opt.leaf_cap = o->leaf_cap > 0 ? o->leaf_cap : 64;
+        opt.leaf_rule = o->leaf_rule;
+        opt.c_d = o->c_d > 0 ? o->c_d : opt.c_d;
+        opt.far_field = o->far_field;
+        opt.lf_grid = o->lf_grid;
+        opt.precision = o->precision;
+        opt.corrections = o->corrections;
+        opt.verbose = o->verbose;
+        opt.wedge_factor = o->wedge_factor > 0 ? o->wedge_factor : opt.wedge_factor;
+        opt.m2l_tile = o->m2l_tile;
+        if (o->p2p_threshold != 0) opt.p2p_threshold = o->p2p_threshold;
+        if (!std::isfinite(o->coupling)) throw std::invalid_argument("non-finite coupling");
+        opt.coupling = o->coupling != 0 ? o->coupling : 1.0;
+        opt.autotune = o->autotune;
+        if (o->slab_mb < 0) throw std::invalid_argument("negative slab size");
+        if (o->slab_mb > 0) opt.slab_mb = o->slab_mb;
+        if (o->hf_template < 0 || o->hf_template > 1) throw std::invalid_argument("unknown high-frequency template rule");
+        opt.hf_template = o->hf_template;
+    }
+    if (opt.precision < FDA_PREC_FP64 || opt.precision > FDA_PREC_BOTH) throw std::invalid_argument("unknown precision");
+    if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");
+    return opt;
+}
+
+int fda_analyze(const fda_geometry *g, double k, double eps, const fda_opts *o, char *buf, size_t len)
+{
+    return guarded([&] {
+        if (!g || !buf) throw std::invalid_argument("null geometry or buffer");
+        const Options opt = parse_opts(o);
+        std::unique_ptr<Plan> P(plan_create_host(g->n_nodes, g->pts, g->nrm, g->w, g->n_elem, g->elem, k, eps, opt));
+        const std::string s = plan_stats(*P);
+        if (s.size() + 1 > len) throw std::invalid_argument("stats buffer too small");
+        std::memcpy(buf, s.c_str(), s.size() + 1);
+        return FDA_OK;
+    });
+}
+
 int fda_build(const fda_geometry *g, double k, double eps, const fda_opts *o, fda_plan **out)
 {
     return guarded([&] {
         if (!g || !out) throw std::invalid_argument("null geometry or output pointer");
         *out = nullptr;
-        Options opt;
-        if (o) {
-            opt.svd_eps = o->svd_eps;
-            opt.lowrank_eps = o->lowrank_eps;
-            opt.leaf_cap = o->leaf_cap > 0 ? o->leaf_cap : 64;
-            opt.leaf_rule = o->leaf_rule;
-            opt.c_d = o->c_d > 0 ? o->c_d : opt.c_d;
-            opt.far_field = o->far_field;
-            opt.lf_grid = o->lf_grid;
-            opt.precision = o->precision;
-            opt.corrections = o->corrections;
-            opt.verbose = o->verbose;
-            opt.wedge_factor = o->wedge_factor > 0 ? o->wedge_factor : opt.wedge_factor;
-            opt.m2l_tile = o->m2l_tile;
-            if (o->p2p_threshold != 0) opt.p2p_threshold = o->p2p_threshold;
-            if (!std::isfinite(o->coupling)) throw std::invalid_argument("non-finite coupling");
-            opt.coupling = o->coupling != 0 ? o->coupling : 1.0;
-            opt.autotune = o->autotune;
-            if (o->slab_mb < 0) throw std::invalid_argument("negative slab size");
-            if (o->slab_mb > 0) opt.slab_mb = o->slab_mb;
-        }
-        if (opt.precision < FDA_PREC_FP64 || opt.precision > FDA_PREC_BOTH) throw std::invalid_argument("unknown precision");
-        if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");
+        const Options opt = parse_opts(o);
         Plan *P = plan_create_host(g->n_nodes, g->pts, g->nrm, g->w, g->n_elem, g->elem, k, eps, opt);
         try {
             device_upload(*P);

@@ -30,6 +30,8 @@ struct Options {
     int corrections = 1;     // build local corrections when elements are supplied
     int verbose = 0;
     double coupling = 1.0;   // Burton-Miller alpha = i coupling / k
+    int hf_template = 0;     // 0: checks on the region each wedge's field is evaluated in, cube-surface
+                             // equivalents; 1: circular check cone, ball equivalents (earlier construction)
     int autotune = 1;        // time the M2L/M2M/L2L chunk shapes on the plan and keep the faster
     int slab_mb = 1024;      // scratch of per-pair translation results per slab (MiB)
     // k of the coupling: alpha = i / alpha_k()
@@ -47,10 +49,24 @@ struct Cube {
     Cube() { for (int &c : child) c = -1; }
 };
 
+// Equivalent and check points of one high-frequency wedge orbit, in the
+// frame of the orbit's representative wedge (relative to the cube centre),
+// with their reduced bases (eqs. eq_svdr, eq_invr).
+struct OrbitTemplate {
+    std::vector<double> X;  // equivalent points, |X| x 3
+    std::vector<double> Y;  // check points, |Y| x 3
+    CMat Vt;                // |X| x s, zero columns past this orbit's own rank
+    CMat W;                 // s x |Y|, zero rows past this orbit's own rank
+    std::vector<double> sing;
+    int rank = 0;           // singular values kept for this orbit (<= s of the level)
+};
+
 // Point templates and pseudo-inverse of one level (section 3.1.2 and eqs.
-// eq_svdr, eq_invr).  Frames: low-frequency templates are axis-aligned cube
-// surfaces; high-frequency templates are built for direction +x and rotated
-// per wedge.
+// eq_svdr, eq_invr).  Low-frequency templates are axis-aligned cube
+// surfaces (X, Y, Vt, W below).  High-frequency levels hold one template per
+// wedge orbit of the 48 signed permutations of the cube (`orbit`); the
+// template of wedge z is that of its orbit mapped by the signed permutation
+// of its frame, which maps the cube onto itself.
 struct LevelTemplate {
     bool hf = false;
     double w = 0;
@@ -62,10 +78,13 @@ struct LevelTemplate {
     CMat W;               // s x |Y|  (Sigma~^-1 U~^H)
     std::vector<double> sing;  // singular values of R
     double theta_cone = 0, r_in = 0, r_out = 0;
+    std::unordered_map<int, OrbitTemplate> orbit;  // high frequency: by representative wedge
+    int n_equiv_max = 0, n_check_max = 0;
 };
 
 struct WedgeFrame {
-    std::array<double, 9> R;   // rotation (row-major) taking the +x template to this wedge
+    std::array<double, 9> R;   // rotation (row-major) taking the +x direction to this wedge
+    std::array<double, 9> G;   // signed permutation (row-major) taking the orbit's representative to this wedge
     int orbit = 0;             // canonical wedge id of its symmetry orbit
     std::array<int, 3> perm;   // signed permutation g: g e_i = sign[i] e_perm[i]
     std::array<int, 3> sign;

@@ -35,6 +35,10 @@ namespace fdbem {
 namespace {
 
 double svd_eps(const Plan &P) { return P.opt.svd_eps > 0 ? P.opt.svd_eps : P.eps; }
+// High-frequency orbit templates fit the field on a skeleton of the points
+// where it is evaluated; between those points the error is about three times
+// the truncation, so by default they truncate at eps / 3.
+double hf_svd_eps(const Plan &P) { return P.opt.svd_eps > 0 ? P.opt.svd_eps : P.eps / 3.0; }
 double lr_eps(const Plan &P) { return P.opt.lowrank_eps > 0 ? P.opt.lowrank_eps : P.eps; }
 
 std::vector<double> cube_surface(int p, double a)
@@ -186,6 +190,186 @@ void rotate(const std::array<double, 9> &R, const std::vector<double> &in, std::
             out[3 * i + a] = R[3 * a] * in[3 * i] + R[3 * a + 1] * in[3 * i + 1] + R[3 * a + 2] * in[3 * i + 2];
 }
 
+// Surface grid of the cube of half-width a with spacing at most h.
+std::vector<double> cube_surface_spacing(double a, double h)
+{
+    return cube_surface(std::max(4, (int)std::ceil(2.0 * a / h) + 1), a);
+}
+
+// Uniform point on the surface of the cube of half-width a, from two
+// uniform numbers in [0, 1) and a face index.
+void cube_surface_point(double a, int face, double u, double v, double *p)
+{
+    const int ax = face >> 1;
+    p[ax] = (face & 1) ? -a : a;
+    p[(ax + 1) % 3] = a * (2.0 * u - 1.0);
+    p[(ax + 2) % 3] = a * (2.0 * v - 1.0);
+}
+
+// Small deterministic generator for the sampling below (splitmix64).
+struct Mix {
+    uint64_t x;
+    uint64_t next()
+    {
+        uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return z ^ (z >> 31);
+    }
+    double uni() { return (next() >> 11) * (1.0 / 9007199254740992.0); }
+};
+
+// Greedy pivoted selection of up to max_k rows of A (n x c), stopping at a
+// relative residual of tol: the columns of A^T.
+std::vector<int> select_rows(const CMat &A, double tol, int max_k)
+{
+    CMat At(A.n, A.m);
+    for (int j = 0; j < A.n; ++j)
+        for (int i = 0; i < A.m; ++i) At(j, i) = A(i, j);
+    return select_columns(At, tol, max_k);
+}
+
+// High-frequency template of one wedge orbit (representative wedge zr of a
+// level of width w).  The outgoing field of the cube's sources is needed
+// only where the method evaluates it:
+//  (a) M2L: at the equivalent points of the target cubes B, whose centre
+//      offsets c_B - c_C are the level's operator offsets of this orbit
+//      (section 3.1.1: same-level pairs outside the near field, in this
+//      wedge), i.e. on the surfaces of the cubes at those offsets;
+//  (b) M2M: at the check points of the parent's templates for the parent
+//      wedges that nest in this wedge, seen from each of the eight child
+//      positions.
+// Check candidates sample (a) and take (b) whole.  Equivalent candidates
+// are a grid on the cube's surface (half-width 1.05 w/2) that encloses the
+// sources; the equivalent points are a column skeleton of the interaction
+// matrix, the check points a row skeleton of what remains, both selected at
+// tolerance 0.05 eps (the sampling of section 3.1.2 with controlling
+// accuracy eps), and R = G(Y, X) is truncated by eq. eq_invr.
+OrbitTemplate hf_orbit_template(const Plan &P, int l, int zr, const std::vector<double> &parent_checks)
+{
+    const LevelInfo &L = P.levels[l];
+    const double w = L.w, lam = P.lambda, k = P.k;
+    const double a = 1.05 * 0.5 * w;
+    // candidate spacing lambda/5, coarser on wide cubes (at most ~4000 candidates)
+    const std::vector<double> Xc = cube_surface_spacing(a, std::max(lam / 5.0, 2.0 * a * std::sqrt(6.0 / 4000.0)));
+    const int nxc = (int)Xc.size() / 3;
+    // (a) the operator offsets of this orbit (canonical frame, units of w)
+    std::vector<std::array<int, 3>> offs;
+    int omin = 1 << 30;
+    for (const auto &ki : P.m2l_keyinfo[l])
+        if (ki[0] == zr) {
+            offs.push_back({ki[1], ki[2], ki[3]});
+            omin = std::min(omin, std::max({std::abs(ki[1]), std::abs(ki[2]), std::abs(ki[3])}));
+        }
+    Mix rng{0x51ed2701ull + 977ull * (uint64_t)zr + 131ull * (uint64_t)l};
+    std::vector<double> Ya;
+    auto add_on_cube = [&](const std::array<int, 3> &o, int n) {
+        for (int t = 0; t < n; ++t) {
+            double p[3];
+            cube_surface_point(a, (int)(rng.next() % 6), rng.uni(), rng.uni(), p);
+            for (int d = 0; d < 3; ++d) Ya.push_back(o[d] * w + p[d]);
+        }
+    };
+    if (!offs.empty()) {
+        // a fixed budget shared by the offsets, at most what resolves one
+        // target cube's surface at lambda/2.5; the nearest offsets, which bound
+        // the accuracy, get at least 48 each
+        const int budget = 24000;
+        const int n_surf = std::max(16, (int)std::ceil(6.0 * std::pow(2.0 * a / (lam / 2.5), 2)));
+        const int per = std::max(1, std::min(n_surf, budget / (int)offs.size()));
+        for (const auto &o : offs) {
+            const int cheb = std::max({std::abs(o[0]), std::abs(o[1]), std::abs(o[2])});
+            add_on_cube(o, cheb == omin ? std::max(per, 48) : per);
+        }
+    }
+    const int nya = (int)Ya.size() / 3, nyb = (int)parent_checks.size() / 3;
+    std::vector<double> Yall(Ya);
+    Yall.insert(Yall.end(), parent_checks.begin(), parent_checks.end());
+    const int nyall = nya + nyb;
+    if (nyall == 0) throw std::runtime_error("high-frequency template without evaluation points");
+    // column skeleton on a subsample of the check candidates
+    std::vector<int> sub;
+    {
+        const int want_a = std::min(nya, 3000), want_b = std::min(nyb, 1500);
+        for (int t = 0; t < want_a; ++t) sub.push_back((int)((int64_t)t * nya / want_a));
+        for (int t = 0; t < want_b; ++t) sub.push_back(nya + (int)((int64_t)t * nyb / want_b));
+    }
+    const int ns = (int)sub.size();
+    const int ell = std::min(ns, 256);
+    CMat Om = gaussian_sketch(ell, ns, 7777 + 31 * (uint64_t)zr + (uint64_t)l);
+    CMat Bsk(ell, nxc);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int j = 0; j < nxc; ++j) {
+        std::vector<cplx> col(ns);
+        for (int i = 0; i < ns; ++i) col[i] = kernel_G(&Yall[3 * (size_t)sub[i]], &Xc[3 * (size_t)j], k);
+        for (int q = 0; q < ell; ++q) {
+            cplx acc = 0.0;
+            for (int i = 0; i < ns; ++i) acc += Om(q, i) * col[i];
+            Bsk(q, j) = acc;
+        }
+    }
+    const double id_tol = 0.05 * hf_svd_eps(P);
+    const std::vector<int> xs = select_columns(Bsk, id_tol, ell - 8);
+    const int nx = (int)xs.size();
+    OrbitTemplate T;
+    T.X.resize(3 * (size_t)nx);
+    for (int t = 0; t < nx; ++t)
+        for (int d = 0; d < 3; ++d) T.X[3 * t + d] = Xc[3 * (size_t)xs[t] + d];
+    // row skeleton of G(all check candidates, X)
+    CMat A(nyall, nx);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nyall; ++i)
+        for (int j = 0; j < nx; ++j) A(i, j) = kernel_G(&Yall[3 * (size_t)i], &T.X[3 * (size_t)j], k);
+    std::vector<int> ys = select_rows(A, id_tol, nx);
+    // oversample: as many again spread over the candidates, so that R is
+    // fitted in the least-squares sense rather than interpolated
+    {
+        std::vector<char> taken(nyall, 0);
+        for (int i : ys) taken[i] = 1;
+        const int extra = std::min((int)ys.size(), nyall - (int)ys.size());
+        for (int t = 0, added = 0; added < extra && t < 4 * nyall; ++t) {
+            const int i = (int)(rng.next() % (uint64_t)nyall);
+            if (!taken[i]) {
+                taken[i] = 1;
+                ys.push_back(i);
+                ++added;
+            }
+        }
+    }
+    T.Y.resize(3 * ys.size());
+    for (size_t t = 0; t < ys.size(); ++t)
+        for (int d = 0; d < 3; ++d) T.Y[3 * t + d] = Yall[3 * (size_t)ys[t] + d];
+    return T;
+}
+
+// R = G(Y, X) = U S V^H of an orbit template, truncated at eps (eq. eq_invr)
+// and padded with zero basis vectors up to the level's common dimension s.
+void finish_orbit(OrbitTemplate &T, double k, double eps)
+{
+    const int ny = (int)T.Y.size() / 3, nx = (int)T.X.size() / 3;
+    CMat R(ny, nx);
+    for (int j = 0; j < nx; ++j)
+        for (int i = 0; i < ny; ++i) R(i, j) = kernel_G(&T.Y[3 * i], &T.X[3 * j], k);
+    SVD d = svd(R);
+    T.sing = d.s;
+    T.rank = std::max(1, truncation_rank(d.s, eps));
+    // Vt and W are filled once the level's s is known
+    T.Vt = d.V;
+    T.W = d.U;
+}
+
+void pad_orbit(OrbitTemplate &T, int s)
+{
+    const int ny = (int)T.Y.size() / 3, nx = (int)T.X.size() / 3;
+    CMat V(nx, s), W(s, ny);
+    for (int c = 0; c < T.rank; ++c) {
+        for (int i = 0; i < nx; ++i) V(i, c) = T.Vt(i, c);
+        for (int i = 0; i < ny; ++i) W(c, i) = std::conj(T.W(i, c)) / T.sing[c];
+    }
+    T.Vt = std::move(V);
+    T.W = std::move(W);
+}
+
 int64_t push_matrix(Plan &P, const CMat &A)
 {
     const int64_t off = (int64_t)P.matpool.size();
@@ -204,9 +388,92 @@ void build_templates(Plan &P)
         const LevelInfo &L = P.levels[l];
         if (L.n_out + L.n_in > 0) needed.push_back(l);
     }
+    // top-down: a high-frequency template samples its parent's check points
     for (int l : needed) {
         const LevelInfo &L = P.levels[l];
-        P.tmpl[l] = L.hf ? hf_template(P, L) : lf_template(P, L.w);
+        if (!L.hf) {
+            P.tmpl[l] = lf_template(P, L.w);
+            continue;
+        }
+        LevelTemplate &T = P.tmpl[l];
+        T.hf = true;
+        T.w = L.w;
+        T.m = L.m;
+        // orbits of the wedges that carry slots at this level
+        std::vector<int> orbits;
+        {
+            std::vector<char> used(L.nwedge, 0);
+            for (size_t t = 0; t < L.out_slot.size(); ++t)
+                if (L.out_slot[t] >= 0 || L.in_slot[t] >= 0) used[t % L.nwedge] = 1;
+            std::vector<char> seen(L.nwedge, 0);
+            for (int z = 0; z < L.nwedge; ++z)
+                if (used[z] && !seen[L.frames[z].orbit]) {
+                    seen[L.frames[z].orbit] = 1;
+                    orbits.push_back(L.frames[z].orbit);
+                }
+        }
+        if (P.opt.hf_template == 1) {
+            // earlier construction: one +x template rotated to each orbit
+            const LevelTemplate H = hf_template(P, L);
+            T.s = H.s;
+            T.theta_cone = H.theta_cone;
+            T.r_in = H.r_in;
+            T.r_out = H.r_out;
+            for (int zr : orbits) {
+                OrbitTemplate O;
+                rotate(L.frames[zr].R, H.X, O.X);
+                rotate(L.frames[zr].R, H.Y, O.Y);
+                O.Vt = H.Vt;
+                O.W = H.W;
+                O.sing = H.sing;
+                O.rank = H.s;
+                T.orbit.emplace(zr, std::move(O));
+            }
+        } else {
+            const bool parent_hf = l > 0 && P.levels[l - 1].hf && P.tmpl[l - 1].hf && !P.tmpl[l - 1].orbit.empty();
+            std::vector<OrbitTemplate> built(orbits.size());
+#pragma omp parallel for schedule(dynamic, 1) if (orbits.size() > 1)
+            for (size_t q = 0; q < orbits.size(); ++q) {
+                const int zr = orbits[q];
+                std::vector<double> pc;
+                if (parent_hf) {
+                    // parent wedges nested in zr, their check points seen from the eight child centres
+                    const LevelInfo &Lp = P.levels[l - 1];
+                    const LevelTemplate &Tp = P.tmpl[l - 1];
+                    for (int zp = 0; zp < Lp.nwedge; ++zp) {
+                        if (wedge_child(zp, Lp.m) != zr) continue;
+                        auto it = Tp.orbit.find(Lp.frames[zp].orbit);
+                        if (it == Tp.orbit.end()) continue;
+                        std::vector<double> Yp;
+                        rotate(Lp.frames[zp].G, it->second.Y, Yp);
+                        for (int oct = 0; oct < 8; ++oct) {
+                            const double off[3] = {((oct & 1) - 0.5) * L.w, (((oct >> 1) & 1) - 0.5) * L.w,
+                                                   (((oct >> 2) & 1) - 0.5) * L.w};
+                            for (size_t t = 0; t < Yp.size() / 3; ++t)
+                                for (int d = 0; d < 3; ++d) pc.push_back(Yp[3 * t + d] - off[d]);
+                        }
+                    }
+                }
+                built[q] = hf_orbit_template(P, l, zr, pc);
+                finish_orbit(built[q], P.k, hf_svd_eps(P));
+            }
+            int s = 0;
+            for (const OrbitTemplate &O : built) s = std::max(s, O.rank);
+            T.s = s;
+            for (size_t q = 0; q < orbits.size(); ++q) {
+                pad_orbit(built[q], s);
+                T.orbit.emplace(orbits[q], std::move(built[q]));
+            }
+        }
+        for (const auto &kv : T.orbit) {
+            T.n_equiv_max = std::max(T.n_equiv_max, (int)kv.second.X.size() / 3);
+            T.n_check_max = std::max(T.n_check_max, (int)kv.second.Y.size() / 3);
+        }
+        if (P.opt.verbose) {
+            std::fprintf(stderr, "[fdbem] level w = %.4g: %zu wedge orbits, s = %d (equivalent <= %d, check <= %d)\n",
+                         L.w, T.orbit.size(), T.s, T.n_equiv_max, T.n_check_max);
+            std::fflush(stderr);
+        }
     }
     P.max_s = 0;
     P.max_Y = 0;
@@ -239,22 +506,21 @@ void build_operators(Plan &P)
         const int nk = P.m2l_nkeys[l];
         if (nk == 0) continue;
         const LevelTemplate &T = P.tmpl[l];
-        const int s = T.s, nx = (int)T.X.size() / 3;
+        const int s = T.s;
         std::vector<CMat> dense(nk), Uf(nk), Vf(nk);
         std::vector<int> rk(nk, -1);
-        std::vector<std::array<double, 9>> R0s;
-        if (L.hf) {
-            R0s.resize(L.nwedge);
-            for (int z = 0; z < L.nwedge; ++z) R0s[z] = L.frames[z].R;  // canonical wedges have g = I
-        }
         const double leps = lr_eps(P);
 #pragma omp parallel for schedule(dynamic, 4)
         for (int key = 0; key < nk; ++key) {
             const auto &ki = P.m2l_keyinfo[l][key];
             std::vector<double> Xb, Xa;  // source (C) and target (B) equivalent points
             double off[3] = {ki[1] * L.w, ki[2] * L.w, ki[3] * L.w};
+            // the canonical offset lies in the orbit's representative wedge, whose
+            // template is in that frame; the target's incoming points are the
+            // reflection (a signed permutation, so again a template of the orbit)
+            const CMat &Vt = L.hf ? T.orbit.at(ki[0]).Vt : T.Vt;
             if (L.hf) {
-                rotate(R0s[ki[0]], T.X, Xb);
+                Xb = T.orbit.at(ki[0]).X;
                 Xa.resize(Xb.size());
                 for (size_t t = 0; t < Xb.size() / 3; ++t)
                     for (int d = 0; d < 3; ++d) Xa[3 * t + d] = off[d] - Xb[3 * t + d];
@@ -264,11 +530,12 @@ void build_operators(Plan &P)
                 for (size_t t = 0; t < Xb.size() / 3; ++t)
                     for (int d = 0; d < 3; ++d) Xa[3 * t + d] = off[d] + Xb[3 * t + d];
             }
+            const int nx = (int)Xb.size() / 3;
             CMat K(nx, nx);
             for (int j = 0; j < nx; ++j)
                 for (int i = 0; i < nx; ++i) K(i, j) = kernel_G(&Xa[3 * i], &Xb[3 * j], P.k);
-            CMat KV = matmul(K, 'N', T.Vt, 'N');
-            CMat Kt = matmul(T.Vt, 'T', KV, 'N');  // s x s
+            CMat KV = matmul(K, 'N', Vt, 'N');
+            CMat Kt = matmul(Vt, 'T', KV, 'N');  // s x s
             SVD d = svd(Kt);
             const int r = truncation_rank(d.s, leps);
             if (2 * r < s) {
@@ -339,14 +606,19 @@ void build_operators(Plan &P)
         for (size_t q = 0; q < keys.size(); ++q) {
             const int zp = keys[q].first, oct = keys[q].second;
             std::vector<double> Yp, Xc;
-            if (Lp.hf)
-                rotate(Lp.frames[zp].R, Tp.Y, Yp);
-            else
+            const CMat *Wp = &Tp.W, *Vc = &Tc.Vt;
+            if (Lp.hf) {
+                const OrbitTemplate &O = Tp.orbit.at(Lp.frames[zp].orbit);
+                rotate(Lp.frames[zp].G, O.Y, Yp);
+                Wp = &O.W;
+            } else
                 Yp = Tp.Y;
             const int zc = Lc.hf ? wedge_child(zp, Lp.m) : 0;
-            if (Lc.hf)
-                rotate(Lc.frames[zc].R, Tc.X, Xc);
-            else
+            if (Lc.hf) {
+                const OrbitTemplate &O = Tc.orbit.at(Lc.frames[zc].orbit);
+                rotate(Lc.frames[zc].G, O.X, Xc);
+                Vc = &O.Vt;
+            } else
                 Xc = Tc.X;
             const double wc = Lc.w;
             const double off[3] = {((oct & 1) - 0.5) * wc, (((oct >> 1) & 1) - 0.5) * wc, (((oct >> 2) & 1) - 0.5) * wc};
@@ -356,8 +628,8 @@ void build_operators(Plan &P)
             CMat E(ny, nx);
             for (int j = 0; j < nx; ++j)
                 for (int i = 0; i < ny; ++i) E(i, j) = kernel_G(&Yp[3 * i], &Xc[3 * j], P.k);
-            CMat EV = matmul(E, 'N', Tc.Vt, 'N');
-            Ms[q] = matmul(Tp.W, 'N', EV, 'N');  // s_p x s_c
+            CMat EV = matmul(E, 'N', *Vc, 'N');
+            Ms[q] = matmul(*Wp, 'N', EV, 'N');  // s_p x s_c
         }
         for (size_t q = 0; q < keys.size(); ++q) mats[keys[q]] = push_matrix(P, Ms[q]);
         // upward list: parent out slots

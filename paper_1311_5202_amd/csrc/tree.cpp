@@ -125,6 +125,7 @@ WedgeFrame wedge_frame(int z, int m)
     // g as a matrix: column i is sign[i] e_perm[i]
     double g[9] = {0};
     for (int i = 0; i < 3; ++i) g[3 * perm[i] + i] = F.sign[i];
+    for (int i = 0; i < 9; ++i) F.G[i] = g[i];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             double t = 0;

@@ -181,6 +181,31 @@ class Plan:
         return json.loads(buf.value.decode())
 
 
+def _opts(**opts):
+    o = _abi.FdaOpts()
+    _abi.check(_abi.lib().fda_default_opts(ctypes.byref(o)))
+    if isinstance(opts.get("precision"), str):
+        opts["precision"] = _abi.PREC[opts["precision"]]
+    for key, val in opts.items():
+        if not hasattr(o, key):
+            raise TypeError(f"unknown option {key}")
+        setattr(o, key, val)
+    return o
+
+
+def analyze(pts, nrm, w, k, eps, **opts) -> dict:
+    """Host-side plan structure without a GPU (fda_analyze): levels, reduced
+    dimensions, pair and operator counts."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    nrm = np.ascontiguousarray(nrm, dtype=np.float64).reshape(-1, 3)
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+    g = _abi.FdaGeometry(w.shape[0], pts.ctypes.data, nrm.ctypes.data, w.ctypes.data, 0, None)
+    o = _opts(**opts)
+    buf = ctypes.create_string_buffer(1 << 22)
+    _abi.check(_abi.lib().fda_analyze(ctypes.byref(g), float(k), float(eps), ctypes.byref(o), buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
 def build(pts, nrm, w, k, eps, elements=None, **opts) -> Plan:
     return Plan(pts, nrm, w, k, eps, elements=elements, **opts)
 

@@ -113,3 +113,27 @@ def test_option_validation():
         with pytest.raises(_abi.FdaError) as e:
             fdb.build(pts, nrm, w, 5.0, 1e-4, **bad)
         assert e.value.code == _abi.FDA_EINVAL
+
+
+def test_reduced_dimension_per_level():
+    """The host plan (no GPU): sphere N = 12,288 at k = 40 has high-frequency
+    M2L at w = lambda and 2 lambda.  Templates fitted on the region where each
+    wedge's field is evaluated keep s at w = lambda at most 50 (the paper
+    reports s = 38 at w = lambda, eps = 1e-4, Fig. 3 caption), well below the
+    earlier circular-cone construction, and the translation operators come
+    out with the low-rank switch of section 4.2 (rank < s/2)."""
+    import synth
+
+    el = synth.octa_sphere(16)
+    p, n, w = fdb.nystrom_nodes(el)
+    k = 40.0
+    lam = 2 * np.pi / k
+    st = fdb.analyze(p, n, w, k, 1e-4)
+    old = fdb.analyze(p, n, w, k, 1e-4, hf_template=1)
+    s_new = {round(L["w"] / lam, 3): L["s"] for L in st["levels"] if L["s"]}
+    s_old = {round(L["w"] / lam, 3): L["s"] for L in old["levels"] if L["s"]}
+    print("s per level (w / lambda: s):", s_new, "earlier construction:", s_old)
+    assert s_new[1.0] <= 50 and s_new[2.0] <= 60
+    assert s_old[1.0] > 1.5 * s_new[1.0]
+    assert st["levels"] and all(L["m2l_pairs_lowrank"] <= L["m2l_pairs"] for L in st["levels"])
+    assert sum(L["m2l_pairs"] for L in st["levels"]) == sum(L["m2l_pairs"] for L in old["levels"])
