@@ -196,7 +196,8 @@ __global__ void k_permute_out(const double2 *__restrict__ res, const int64_t *__
     out[j] = v;
 }
 
-// Near field.  One 64-lane wavefront per target leaf: lane = t + nt q for
+// Near field.  One 64-lane workgroup per target leaf, leaves launched in
+// decreasing order of work: lane = t + nt q for
 // target t of the nt targets and source slice q of S = 64 / nt, so small
 // leaves still fill the wavefront; each lane takes two sources per step, and
 // the slices are added in order q = 0, 1, .. with cross-lane shuffles.  The
@@ -244,16 +245,16 @@ __device__ __forceinline__ typename Cx<R>::T kernel_op(R dx, R dy, R dz, R nxx, 
 }
 
 template <int OPK, typename R>
-__global__ __launch_bounds__(256) void k_p2p(int n_leaf, const int64_t *__restrict__ ts, const int64_t *__restrict__ te,
+__global__ __launch_bounds__(64) void k_p2p(int n_leaf, const int64_t *__restrict__ ts, const int64_t *__restrict__ te,
                                              const int *__restrict__ ptr, const int64_t *__restrict__ ss,
                                              const int64_t *__restrict__ se, const PN *__restrict__ pn,
                                              const double2 *__restrict__ dens, double2 *__restrict__ res, double k,
                                              double alpha_im)
 {
     using C = typename Cx<R>::T;
-    const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int leaf = blockIdx.x;
     if (leaf >= n_leaf) return;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x;
     const R kr = (R)k, ik = (R)alpha_im;
     const int64_t t0 = ts[leaf], t1 = te[leaf];
     const int e0 = ptr[leaf], e1 = ptr[leaf + 1];
@@ -1323,11 +1324,43 @@ void device_upload(Plan &P)
         D.pn = (void *)dupload(D, pnh);
     }
     D.n_leaf = (int)P.leaves.size();
-    D.p2p_ts = dupload(D, P.p2p_tgt_start);
-    D.p2p_te = dupload(D, P.p2p_tgt_end);
-    D.p2p_ptr = dupload(D, P.p2p_ptr);
-    D.p2p_ss = dupload(D, P.p2p_src_start);
-    D.p2p_se = dupload(D, P.p2p_src_end);
+    {
+        // target leaves in decreasing order of P2P work (one wavefront each:
+        // per block of 64 targets, the source steps of 64/nt slices), so the
+        // longest wavefronts start first and the short ones fill the tail
+        const int nl = (int)P.p2p_tgt_start.size();
+        std::vector<double> work(nl, 0.0);
+        for (int t = 0; t < nl; ++t) {
+            const int64_t nt_all = P.p2p_tgt_end[t] - P.p2p_tgt_start[t];
+            for (int64_t ib = 0; ib < nt_all; ib += 64) {
+                const int64_t nt = std::min<int64_t>(64, nt_all - ib), S = 64 / nt;
+                for (int e = P.p2p_ptr[t]; e < P.p2p_ptr[t + 1]; ++e)
+                    work[t] += (double)((P.p2p_src_end[e] - P.p2p_src_start[e] + S - 1) / S);
+            }
+        }
+        std::vector<int> order(nl);
+        for (int t = 0; t < nl; ++t) order[t] = t;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+        std::vector<int64_t> ts(nl), te(nl), ss, se;
+        std::vector<int> ptr(nl + 1, 0);
+        ss.reserve(P.p2p_src_start.size());
+        se.reserve(P.p2p_src_end.size());
+        for (int q = 0; q < nl; ++q) {
+            const int t = order[q];
+            ts[q] = P.p2p_tgt_start[t];
+            te[q] = P.p2p_tgt_end[t];
+            for (int e = P.p2p_ptr[t]; e < P.p2p_ptr[t + 1]; ++e) {
+                ss.push_back(P.p2p_src_start[e]);
+                se.push_back(P.p2p_src_end[e]);
+            }
+            ptr[q + 1] = (int)ss.size();
+        }
+        D.p2p_ts = dupload(D, ts);
+        D.p2p_te = dupload(D, te);
+        D.p2p_ptr = dupload(D, ptr);
+        D.p2p_ss = dupload(D, ss);
+        D.p2p_se = dupload(D, se);
+    }
     // templates
     const int nlev = (int)P.levels.size();
     D.n_lev = nlev;
@@ -1610,7 +1643,9 @@ template <typename R, typename O>
 static void launch_p2p(Plan &P, Device &D, int op, hipStream_t st)
 {
     const int opk = (op == 0 || op == 3) ? OPK_H : (op == 1 || op == 4) ? OPK_G : OPK_T1;
-    const dim3 g((D.n_leaf + 3) / 4), b(256);
+    // one 64-lane workgroup per target leaf: a finished wavefront frees its
+    // slot at once instead of waiting for the slowest leaf of its group
+    const dim3 g(D.n_leaf), b(64);
     const double ai = 1.0 / P.opt.alpha_k(P.k);
     if (opk == OPK_H)
         hipLaunchKernelGGL((k_p2p<OPK_H, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
