@@ -37,6 +37,17 @@ BATCH = {"c3": (64, 2, (10_000, 100_000), (5.0, 60.0))}
 LEARNED = {"c4": {"train": 16, "held_out": 8, "n_split": 16, "kd_train": (20.0, 80.0), "kd_test": 50.0,
                   "seed_train": 3, "seed_test": 4}}
 
+# radiation of a pulsating unit sphere (q = du/dn = 1, exact u = 1/(1 - ik)):
+# k = 2 pi ... 32 pi with elements of size about lambda / 5 (8 n^2 octahedral
+# elements, n = round(sqrt(720 (k / 2 pi)^2 / 8)): 648 ... 184,832 elements)
+RADIATION = {"radiation": [2 * math.pi * f for f in (1, 2, 4, 8, 16)]}
+
+# the summation of Table 1 (section 5.1): (octahedral n, k / pi, eps) about
+# 20 nodes per wavelength, N = 73,008 ... 4,732,608 (the paper's 73,728 ...
+# 4,718,592), improved method and the original one it is compared with
+TABLE1 = {"table1": [(39, 8, 1e-4), (39, 8, 1e-6), (39, 8, 1e-8), (78, 16, 1e-4), (78, 16, 1e-6),
+                     (157, 32, 1e-4), (157, 32, 1e-6), (314, 64, 1e-4)]}
+
 WORKLOADS = {
     # name: (octahedral split n, k, eps, description)
     "c1": (8, 5.0, 1e-4, "unit sphere, 512 quadratic triangles, N=3072, k=5 (kD=10), eps=1e-4"),
@@ -299,6 +310,149 @@ def learned_main(args, fdb, synth, torch) -> int:
     return 0
 
 
+def table1_main(args, fdb, synth, torch) -> int:
+    """Table 1 (section 5.1): one summation with the Table-1 kernel
+    G + alpha dG/dn_y on random densities, for the improved method and the
+    original one (original = 1: equivalent densities with uncompressed R+ and
+    K, no low-rank M2L).  Reports per case the M2L time, the upward-pass time
+    (S2M + M2M), the plan's device memory and operator bytes, and eps_a on
+    200 seeded rows against the oracle's dense sums (the CPU leg)."""
+    import numpy as np
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    cases = TABLE1[args.workload]
+    if args.cases:
+        cases = [cases[int(i)] for i in args.cases.split(",")]
+    rows = []
+    for n_oct, kp, eps in cases:
+        el = synth.octa_sphere(n_oct)
+        pts, nrm, w = fdb.nystrom_nodes(el)
+        k = kp * math.pi
+        u_host = synth.random_densities(len(w), 3)
+        u = torch.from_numpy(u_host).cuda()
+        for original in (0, 1):
+            row = {"N": int(len(w)), "k_over_pi": kp, "eps": eps, "method": "original" if original else "improved"}
+            try:
+                t0 = time.perf_counter()
+                plan = fdb.build(pts, nrm, w, k, eps, original=original, coupling=1.0, verbose=1)
+                row["build_s"] = time.perf_counter() - t0
+            except fdb.FdaError as e:  # operators beyond the chunk kernel's LDS
+                row["error"] = str(e)
+                rows.append(row)
+                log(f"[bench] table1 {row}")
+                continue
+            out = torch.empty_like(u)
+            for _ in range(2):
+                plan.matvec(u, "RAW_T1", out=out)
+            plan.set_timing(True)
+            for _ in range(max(3, args.steps // 4)):
+                plan.matvec(u, "RAW_T1", out=out)
+            ph = plan.phase_times()
+            plan.set_timing(False)
+            st = plan.stats()
+            row.update({"t_m2l_ms": ph["m2l"], "t_up_ms": ph["s2m"] + ph["m2m"], "t_total_ms": sum(ph.values()),
+                        "device_gb": st["device_bytes"] / 1e9, "operator_gb": st["matpool_bytes"] / 1e9,
+                        "s_per_level": [L["s"] for L in st["levels"] if L["s"]]})
+            got = out.cpu().numpy()
+            plan.close()
+            if not args.no_cpu_baseline:
+                import oracle
+
+                rr = np.sort(np.random.default_rng(7).choice(len(w), 200, replace=False))
+                ref = oracle.dense_rows(pts, nrm, w, u_host, k, "T1", rows=rr)
+                row["eps_a"] = oracle.rel_l2(got[rr], ref)
+            rows.append(row)
+            log(f"[bench] table1 {row}")
+    # ratios original / improved per case
+    ratios = []
+    for a, b in zip(rows[::2], rows[1::2]):
+        if "t_m2l_ms" in a and "t_m2l_ms" in b:
+            ratios.append({"N": a["N"], "eps": a["eps"], "m2l": b["t_m2l_ms"] / a["t_m2l_ms"],
+                           "up": b["t_up_ms"] / a["t_up_ms"], "memory": b["device_gb"] / a["device_gb"]})
+    imp = [r for r in rows if r["method"] == "improved" and "t_total_ms" in r]
+    last = imp[-1]
+    out = {
+        "metric": "Table-1 summation (section 5.1): improved FDA time per summation at the largest N run",
+        "value": last["t_total_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": len(rows),
+        "warmup": 2,
+        "ms_per_step": last["t_total_ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "unit sphere, ~20 nodes per wavelength, Table-1 kernel G + (i/k) dG/dn_y, "
+                               "random densities, improved vs original FDA", "parallelism": "single GPU"},
+        "rows": rows,
+        "original_over_improved": ratios,
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def radiation_main(args, fdb, synth, torch) -> int:
+    """Neumann problem of the pulsating sphere for each k of the series:
+    right-hand side (S + alpha M) q - alpha q / 2 by fda_rhs_neumann, GMRES on
+    the Burton-Miller operator to tol = eps, error against 1/(1 - ik)."""
+    import numpy as np
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    rows = []
+    eps = args.eps
+    for k in RADIATION[args.workload]:
+        n = max(2, int(round(math.sqrt(720.0 * (k / (2 * math.pi)) ** 2 / 8.0))))
+        el = synth.octa_sphere(n)
+        pts, nrm, w = fdb.nystrom_nodes(el)
+        t0 = time.perf_counter()
+        plan = fdb.build(pts, nrm, w, k, eps, elements=el, corrections=3, coupling=args.coupling)
+        t_build = time.perf_counter() - t0
+        q = torch.ones(len(w), dtype=torch.complex128, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rhs = plan.rhs_neumann(q)
+        x, info = plan.solve(rhs, eps, maxit=500, restart=500, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        u = x.cpu().numpy()
+        ref = 1.0 / (1.0 - 1j * k)  # the closed form the paper quotes (section 5.2)
+        err_l2 = float(np.linalg.norm(u - ref) / (abs(ref) * math.sqrt(len(u))))
+        err_max = float(np.max(np.abs(u - ref)) / abs(ref))
+        row = {"k_over_pi": round(k / math.pi, 6), "n_elem": int(el.shape[0]), "N": int(len(w)),
+               "build_s": t_build, "iterations": info["iterations"], "status": info["status"],
+               "solve_s": t_solve, "ms_per_iteration": 1e3 * t_solve / max(1, info["iterations"]),
+               "rel_err_l2": err_l2, "rel_err_max": err_max,
+               "plan_device_gb": plan.stats().get("device_bytes", 0) / 1e9}
+        log(f"[bench] radiation {row}")
+        rows.append(row)
+        plan.close()
+    last = rows[-1]
+    out = {
+        "metric": "pulsating-sphere radiation solve (GMRES to eps) at the largest k of the series",
+        "value": last["solve_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": len(rows),
+        "warmup": 0,
+        "ms_per_step": last["ms_per_iteration"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "pulsating unit sphere, q = 1, k = 2pi..32pi, elements ~lambda/5 "
+                               f"(N = {rows[0]['N']}..{last['N']}), eps = GMRES tol = {eps:g}",
+                   "alpha": f"{args.coupling:g}i/k", "parallelism": "single GPU"},
+        "series": rows,
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def batch_main(args, fdb, synth, torch) -> int:
     """Uneven instances: one graph launch applies every instance's FP32
     mat-vec; compared with the same mat-vecs launched one plan at a time."""
@@ -371,7 +525,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=os.environ.get("FDBEM_WORKLOAD", "c5"),
-                    choices=sorted(WORKLOADS) + sorted(BATCH) + sorted(LEARNED))
+                    choices=sorted(WORKLOADS) + sorted(BATCH) + sorted(LEARNED) + sorted(RADIATION) + sorted(TABLE1))
+    ap.add_argument("--cases", default="", help="table1 workload: comma-separated case indices (default: all)")
+    ap.add_argument("--eps", type=float, default=1e-4, help="radiation workload: FDA eps and GMRES tolerance")
     ap.add_argument("--instances", type=int, default=0, help="batched workload: number of instances (0: 64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0)
@@ -402,6 +558,10 @@ def main() -> int:
         return batch_main(args, fdb, synth, torch)
     if args.workload in LEARNED:
         return learned_main(args, fdb, synth, torch)
+    if args.workload in RADIATION:
+        return radiation_main(args, fdb, synth, torch)
+    if args.workload in TABLE1:
+        return table1_main(args, fdb, synth, torch)
     n_split, k, eps, desc = WORKLOADS[args.workload]
     el = synth.octa_sphere(n_split)
     pts, nrm, w = fdb.nystrom_nodes(el)

@@ -80,7 +80,8 @@ typedef struct {
                            low-frequency templates and eps/3 for the high-frequency ones
                            (fitted on a skeleton of the region the field is evaluated in,
                            they err about three times the truncation between its points) */
-    double lowrank_eps; /* truncation of the low-rank M2L factors (eq. eq_lrdk); 0 -> eps */
+    double lowrank_eps; /* truncation of the low-rank M2L factors (eq. eq_lrdk); 0 -> eps;
+                           < 0: no low-rank factors (every M2L applies K~)               */
     int leaf_cap;       /* max points per octree leaf; 0 -> 64                            */
     int leaf_rule;      /* 0: leaves are low-frequency cubes (w < lambda)                  */
     double c_d;         /* high-frequency near-field constant (section 3.1.1); 0 -> 1/pi  */
@@ -108,6 +109,11 @@ typedef struct {
                            (M2L target cubes, parent check points), equivalent points on the
                            cube's surface; 1: the earlier circular check cone and ball of
                            equivalent points rotated to each wedge (larger s)               */
+    int original;       /* 1: the method the paper improves on (section 4, Table 1), for
+                           comparison: translations act on the equivalent densities with
+                           the uncompressed pseudo-inverses R+ and M2L matrices K (no
+                           matrix reduction of section 4.1, no low-rank M2L of section
+                           4.2); same results up to rounding, larger operators; 0 default */
 } fda_opts;
 
 typedef struct fda_plan fda_plan;

@@ -42,7 +42,8 @@ class FdaOpts(ctypes.Structure):
                 ("coupling", ctypes.c_double),
                 ("autotune", ctypes.c_int),
                 ("slab_mb", ctypes.c_int),
-                ("hf_template", ctypes.c_int)]
+                ("hf_template", ctypes.c_int),
+                ("original", ctypes.c_int)]
 
 
 class FdaError(RuntimeError):

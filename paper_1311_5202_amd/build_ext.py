@@ -30,8 +30,10 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, *COMMON, *DEVICE, "-fopenmp", "-c", src, "-o", obj]
     else:
-        # host-only translation units (set-up, ABI): plain C++ with OpenMP
-        cmd = [HIPCC, *COMMON, "-x", "c++", "-fopenmp", "-c", src, "-o", obj]
+        # host-only translation units (set-up): plain C++ with OpenMP; complex
+        # products by the textbook formula (no Inf/NaN recovery calls), the
+        # set-up's values are finite and moderate
+        cmd = [HIPCC, *COMMON, "-x", "c++", "-fopenmp", "-fcx-limited-range", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

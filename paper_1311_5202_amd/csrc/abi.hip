@@ -87,6 +87,7 @@ int fda_default_opts(fda_opts *o)
     o->autotune = 1;
     o->slab_mb = 0;
     o->hf_template = 0;
+    o->original = 0;
     return FDA_OK;
 }
 
@@ -146,6 +147,8 @@ static Options parse_opts(const fda_opts *o)
         if (o->slab_mb > 0) opt.slab_mb = o->slab_mb;
         if (o->hf_template < 0 || o->hf_template > 1) throw std::invalid_argument("unknown high-frequency template rule");
         opt.hf_template = o->hf_template;
+        if (o->original < 0 || o->original > 1) throw std::invalid_argument("original must be 0 or 1");
+        opt.original = o->original;
     }
     if (opt.precision < FDA_PREC_FP64 || opt.precision > FDA_PREC_BOTH) throw std::invalid_argument("unknown precision");
     if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");

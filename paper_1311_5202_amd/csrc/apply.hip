@@ -1394,20 +1394,22 @@ void device_upload(Plan &P)
         std::vector<double2> mp(P.matpool.size());
         for (size_t i = 0; i < mp.size(); ++i) mp[i] = make_double2(P.matpool[i].real(), P.matpool[i].imag());
         D.mat = dupload(D, mp);
-        D.m2m.resize(nlev);
-        D.m2l.resize(nlev);
-        D.l2l.resize(nlev);
-        for (int l = 0; l < nlev; ++l) {
-            D.m2m[l] = upload_gemv(D, P.m2m_lists[l]);
-            D.m2l[l] = upload_gemv(D, P.m2l_lists[l]);
-            D.l2l[l] = upload_gemv(D, P.l2l_lists[l]);
-        }
         int maxsh = 65536;
         (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, D.device);
         // M2L mode: 3 operator chunks with per-pair results summed per output
         // (default, deterministic), 0 operator chunks with atomic adds, 1
         // per-target GEMV, 2 workgroup target tiles
         D.m2l_mode = P.opt.m2l_tile < 0 ? 1 : P.opt.m2l_tile > 1 ? 2 : P.opt.m2l_tile == 1 ? 0 : 3;
+        // per-output GEMV lists: the translations of the GEMV and tile schedules
+        D.m2m.resize(nlev);
+        D.m2l.resize(nlev);
+        D.l2l.resize(nlev);
+        if (D.m2l_mode == 1 || D.m2l_mode == 2)
+            for (int l = 0; l < nlev; ++l) {
+                D.m2m[l] = upload_gemv(D, P.m2m_lists[l]);
+                D.m2l[l] = upload_gemv(D, P.m2l_lists[l]);
+                D.l2l[l] = upload_gemv(D, P.l2l_lists[l]);
+            }
         if (D.m2l_mode == 3) {
             // slabs keep the scratch of per-pair results near 1 GiB
             D.m2ls.resize(nlev);

@@ -66,6 +66,12 @@ static SVD svd_tall(const CMat &A)
     CMat V(n, n);
     for (int i = 0; i < n; ++i) V(i, i) = 1.0;
     const double tol = 1e-15;
+    // a rotation whose coupling is below rounding of the whole matrix changes
+    // nothing that matters: skipping it lets columns at the noise level (a
+    // numerically rank-deficient A) stop rotating instead of running every sweep
+    double fro2 = 0.0;
+    for (const cplx &v : A.a) fro2 += std::norm(v);
+    const double negligible = 1e-32 * fro2;
     for (int sweep = 0; sweep < 60; ++sweep) {
         double off = 0.0;
         for (int j = 0; j < n - 1; ++j)
@@ -79,7 +85,7 @@ static SVD svd_tall(const CMat &A)
                     ga += std::conj(wj[i]) * wk[i];
                 }
                 const double ag = std::abs(ga);
-                if (ag == 0.0 || ag <= tol * std::sqrt(al * be)) continue;
+                if (ag == 0.0 || ag <= tol * std::sqrt(al * be) || ag <= negligible) continue;
                 off = std::max(off, ag / std::sqrt(al * be));
                 const cplx ph = std::conj(ga) / ag;  // e^{-i phi}
                 const double zeta = (be - al) / (2.0 * ag);
@@ -215,6 +221,74 @@ CMat gaussian_sketch(int k, int m, uint64_t seed)
         S.a[t] = cplx(r * std::cos(2 * M_PI * u2), r * std::sin(2 * M_PI * u2)) * sc;
     }
     return S;
+}
+
+void orthonormalize(CMat &A)
+{
+    const int m = A.m, n = A.n;
+    for (int j = 0; j < n; ++j) {
+        cplx *aj = A.col(j);
+        double n0 = 0.0;
+        for (int i = 0; i < m; ++i) n0 += std::norm(aj[i]);
+        for (int pass = 0; pass < 2; ++pass)
+            for (int q = 0; q < j; ++q) {
+                const cplx *aq = A.col(q);
+                cplx d = 0.0;
+                for (int i = 0; i < m; ++i) d += std::conj(aq[i]) * aj[i];
+                for (int i = 0; i < m; ++i) aj[i] -= d * aq[i];
+            }
+        double nr = 0.0;
+        for (int i = 0; i < m; ++i) nr += std::norm(aj[i]);
+        if (!(nr > 1e-28 * n0) || nr == 0.0) {
+            // dependent column: take the coordinate vector least covered so far
+            for (int e = 0; e < m; ++e) {
+                for (int i = 0; i < m; ++i) aj[i] = i == e ? 1.0 : 0.0;
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int q = 0; q < j; ++q) {
+                        const cplx *aq = A.col(q);
+                        cplx d = 0.0;
+                        for (int i = 0; i < m; ++i) d += std::conj(aq[i]) * aj[i];
+                        for (int i = 0; i < m; ++i) aj[i] -= d * aq[i];
+                    }
+                nr = 0.0;
+                for (int i = 0; i < m; ++i) nr += std::norm(aj[i]);
+                if (nr > 0.25) break;
+            }
+        }
+        const double inv = 1.0 / std::sqrt(nr);
+        for (int i = 0; i < m; ++i) aj[i] *= inv;
+    }
+}
+
+bool lowrank_factor(const CMat &A, double eps, int max_r, uint64_t seed, CMat &U, CMat &V, int &r)
+{
+    const int m = A.m, n = A.n;
+    const int ell = std::min(std::min(m, n), max_r + 8);
+    if (ell <= 0) return false;
+    // range of A from A (A^H A) Omega, orthonormalised between the products
+    CMat Om = gaussian_sketch(n, ell, seed);  // n x ell
+    CMat Y = matmul(A, 'N', Om, 'N');         // m x ell
+    orthonormalize(Y);
+    CMat Z = matmul(A, 'C', Y, 'N');          // n x ell
+    orthonormalize(Z);
+    CMat Q = matmul(A, 'N', Z, 'N');          // m x ell
+    orthonormalize(Q);
+    CMat B = matmul(Q, 'C', A, 'N');          // ell x n
+    SVD d = svd(B);
+    r = truncation_rank(d.s, eps);
+    if (r > max_r || r >= ell) return false;
+    r = std::max(r, 1);
+    U = CMat(m, r);
+    V = CMat(r, n);
+    for (int c = 0; c < r; ++c) {
+        for (int i = 0; i < m; ++i) {
+            cplx acc = 0.0;
+            for (int q = 0; q < ell; ++q) acc += Q(i, q) * d.U(q, c);
+            U(i, c) = acc;
+        }
+        for (int j = 0; j < n; ++j) V(c, j) = d.s[c] * std::conj(d.V(j, c));
+    }
+    return true;
 }
 
 }  // namespace fdbem

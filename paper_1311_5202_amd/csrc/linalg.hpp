@@ -47,4 +47,13 @@ std::vector<int> select_columns(const CMat &A, double tol, int max_k);
 // (complex), deterministic in seed.
 CMat gaussian_sketch(int k, int m, uint64_t seed);
 
+// Orthonormal columns spanning those of A (Gram-Schmidt twice); a column
+// that vanishes is replaced by a coordinate vector orthogonal to the rest.
+void orthonormalize(CMat &A);
+
+// Factors A ~= U V (U: m x r, V: r x n) truncated at sigma_i >= eps sigma_1,
+// found by a randomized range finder with one power iteration when the
+// eps-rank is at most max_r; returns false (and leaves U, V) otherwise.
+bool lowrank_factor(const CMat &A, double eps, int max_r, uint64_t seed, CMat &U, CMat &V, int &r);
+
 }  // namespace fdbem

@@ -32,6 +32,8 @@ struct Options {
     double coupling = 1.0;   // Burton-Miller alpha = i coupling / k
     int hf_template = 0;     // 0: checks on the region each wedge's field is evaluated in, cube-surface
                              // equivalents; 1: circular check cone, ball equivalents (earlier construction)
+    int original = 0;        // 1: translations on equivalent densities with uncompressed R+ and K, no
+                             // low-rank M2L (the paper's comparison method, Table 1)
     int autotune = 1;        // time the M2L/M2M/L2L chunk shapes on the plan and keep the faster
     int slab_mb = 1024;      // scratch of per-pair translation results per slab (MiB)
     // k of the coupling: alpha = i / alpha_k()

@@ -23,6 +23,7 @@
 // * Low-rank M2L (eq. eq_lrdk): K~ ~= U^ V^ with V^ = S^ Q^^H, truncating
 //   sigma < eps sigma_1; used iff its rank r < s/2, else K~ is applied.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -88,6 +89,28 @@ void finish_template(LevelTemplate &T, double k, double eps)
     }
 }
 
+// The original method of the paper (Table 1's comparison) keeps the
+// equivalent densities themselves: basis V~ -> I (|X| x |X|, zero columns
+// up to s_out) and W -> V~ S~^-1 U~^H = R^+ (rows past |X| zero), so every
+// translation acts in dimension |X| with the uncompressed R^+ (eq. eq_invr)
+// and K; the products equal those of the reduced basis up to rounding.
+void to_original_basis(CMat &Vt, CMat &W, int &s, int nx, int s_out = 0)
+{
+    const int so = std::max(nx, s_out);
+    const int ny = W.n;
+    CMat I(nx, so), Rp(so, ny);
+    for (int i = 0; i < nx; ++i) I(i, i) = 1.0;
+    for (int c = 0; c < s; ++c)
+        for (int j = 0; j < ny; ++j) {
+            const cplx wv = W(c, j);
+            if (wv == cplx(0.0)) continue;
+            for (int i = 0; i < nx; ++i) Rp(i, j) += Vt(i, c) * wv;
+        }
+    Vt = std::move(I);
+    W = std::move(Rp);
+    s = so;
+}
+
 LevelTemplate lf_template(const Plan &P, double w)
 {
     LevelTemplate T;
@@ -98,6 +121,7 @@ LevelTemplate lf_template(const Plan &P, double w)
     T.X = cube_surface(p, 1.05 * 0.5 * w);
     T.Y = cube_surface(p, 2.95 * 0.5 * w);
     finish_template(T, P.k, svd_eps(P));
+    if (P.opt.original) to_original_basis(T.Vt, T.W, T.s, (int)T.X.size() / 3);
     return T;
 }
 
@@ -388,13 +412,16 @@ void build_templates(Plan &P)
         const LevelInfo &L = P.levels[l];
         if (L.n_out + L.n_in > 0) needed.push_back(l);
     }
+    // low-frequency templates are independent of each other: one level per thread
+    std::vector<int> lf_levels;
+    for (int l : needed)
+        if (!P.levels[l].hf) lf_levels.push_back(l);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (size_t q = 0; q < lf_levels.size(); ++q) P.tmpl[lf_levels[q]] = lf_template(P, P.levels[lf_levels[q]].w);
     // top-down: a high-frequency template samples its parent's check points
     for (int l : needed) {
         const LevelInfo &L = P.levels[l];
-        if (!L.hf) {
-            P.tmpl[l] = lf_template(P, L.w);
-            continue;
-        }
+        if (!L.hf) continue;
         LevelTemplate &T = P.tmpl[l];
         T.hf = true;
         T.w = L.w;
@@ -414,7 +441,8 @@ void build_templates(Plan &P)
         }
         if (P.opt.hf_template == 1) {
             // earlier construction: one +x template rotated to each orbit
-            const LevelTemplate H = hf_template(P, L);
+            LevelTemplate H = hf_template(P, L);
+            if (P.opt.original) to_original_basis(H.Vt, H.W, H.s, (int)H.X.size() / 3);
             T.s = H.s;
             T.theta_cone = H.theta_cone;
             T.r_in = H.r_in;
@@ -460,10 +488,17 @@ void build_templates(Plan &P)
             int s = 0;
             for (const OrbitTemplate &O : built) s = std::max(s, O.rank);
             T.s = s;
+            int s_orig = 0;
+            for (const OrbitTemplate &O : built) s_orig = std::max(s_orig, (int)O.X.size() / 3);
             for (size_t q = 0; q < orbits.size(); ++q) {
                 pad_orbit(built[q], s);
+                if (P.opt.original) {
+                    int so = s;
+                    to_original_basis(built[q].Vt, built[q].W, so, (int)built[q].X.size() / 3, s_orig);
+                }
                 T.orbit.emplace(orbits[q], std::move(built[q]));
             }
+            if (P.opt.original) T.s = s_orig;
         }
         for (const auto &kv : T.orbit) {
             T.n_equiv_max = std::max(T.n_equiv_max, (int)kv.second.X.size() / 3);
@@ -510,8 +545,28 @@ void build_operators(Plan &P)
         std::vector<CMat> dense(nk), Uf(nk), Vf(nk);
         std::vector<int> rk(nk, -1);
         const double leps = lr_eps(P);
+        // low-rank M2L (section 4.2) unless disabled (lowrank_eps < 0) or the
+        // original method is requested
+        const bool use_lowrank = !P.opt.original && P.opt.lowrank_eps >= 0;
+        std::atomic<int> done{0};
+        const auto t_lev = std::chrono::steady_clock::now();
+        auto last = t_lev;
 #pragma omp parallel for schedule(dynamic, 4)
         for (int key = 0; key < nk; ++key) {
+            if (P.opt.verbose) {
+                // a progress line about every 30 s on long levels
+                const int d = done.fetch_add(1) + 1;
+#pragma omp critical(fdbem_progress)
+                {
+                    const auto now = std::chrono::steady_clock::now();
+                    if (std::chrono::duration<double>(now - last).count() > 30.0) {
+                        last = now;
+                        std::fprintf(stderr, "[fdbem] M2L operators of level %d: %d of %d (%.0f s)\n", l, d, nk,
+                                     std::chrono::duration<double>(now - t_lev).count());
+                        std::fflush(stderr);
+                    }
+                }
+            }
             const auto &ki = P.m2l_keyinfo[l][key];
             std::vector<double> Xb, Xa;  // source (C) and target (B) equivalent points
             double off[3] = {ki[1] * L.w, ki[2] * L.w, ki[3] * L.w};
@@ -536,14 +591,10 @@ void build_operators(Plan &P)
                 for (int i = 0; i < nx; ++i) K(i, j) = kernel_G(&Xa[3 * i], &Xb[3 * j], P.k);
             CMat KV = matmul(K, 'N', Vt, 'N');
             CMat Kt = matmul(Vt, 'T', KV, 'N');  // s x s
-            SVD d = svd(Kt);
-            const int r = truncation_rank(d.s, leps);
-            if (2 * r < s) {
-                CMat U(s, r), V(r, s);
-                for (int c = 0; c < r; ++c) {
-                    for (int i = 0; i < s; ++i) U(i, c) = d.U(i, c);
-                    for (int j = 0; j < s; ++j) V(c, j) = d.s[c] * std::conj(d.V(j, c));
-                }
+            // low rank when the eps-rank r is below s/2 (strict, section 4.2)
+            CMat U, V;
+            int r = 0;
+            if (use_lowrank && lowrank_factor(Kt, leps, (s - 1) / 2, 0x9e37ull * (uint64_t)(key + 1) + (uint64_t)l, U, V, r)) {
                 Uf[key] = std::move(U);
                 Vf[key] = std::move(V);
                 rk[key] = r;

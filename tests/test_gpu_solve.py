@@ -162,3 +162,30 @@ def test_conjugate_coupling_operator_and_solve(torch):
     assert info["iterations"] < info_p["iterations"]
     plan.close()
     plan_p.close()
+
+
+def test_radiation_series_small_k(torch):
+    """Section 5.2: the pulsating sphere (q = 1) at k = 2 pi and 4 pi with
+    elements of about lambda / 5 (648 and 2888 elements; the paper uses 720
+    and 2880), right-hand side from fda_rhs_neumann, GMRES to tol = eps =
+    1e-4: the surface potential matches 1/(1 - ik), the error falls as the
+    mesh is refined with k, and the paper's alpha = i/k converges at these
+    characteristic frequencies of the sphere."""
+    import paper_1311_5202_amd as fdb
+
+    errs = []
+    for k, n in ((2 * np.pi, 9), (4 * np.pi, 19)):
+        el = synth.octa_sphere(n)
+        pts, nrm, w = fdb.nystrom_nodes(el)
+        print(f"[radiation] k={k:.4f} N={len(w)}", flush=True)
+        plan = fdb.build(pts, nrm, w, k, 1e-4, elements=el, corrections=3)
+        q = torch.ones(len(w), dtype=torch.complex128, device="cuda")
+        x, info = plan.solve(plan.rhs_neumann(q), 1e-4, maxit=200, restart=200)
+        u = x.cpu().numpy()
+        ref = mie.pulsating_sphere(k)
+        err = np.linalg.norm(u - ref) / (abs(ref) * np.sqrt(len(u)))
+        print(f"[radiation] iterations {info['iterations']}, relative L2 error {err:.2e}", flush=True)
+        assert info["status"] == 0
+        errs.append(err)
+        plan.close()
+    assert errs[0] <= 5e-3 and errs[1] <= errs[0]
