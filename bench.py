@@ -183,7 +183,7 @@ def train_learned(fdb, synth, density: float, coupling: float, epochs: int, log)
                  "loss_first": sum(first), "loss_last": sum(last)}
 
 
-def gmres_compare(fdb, synth, plan, tol: float, coupling: float, epochs: int, log):
+def gmres_compare(fdb, synth, plan, tol: float, coupling: float, epochs: int, log, maxit: int = 200):
     """Time-to-tol of plain FP64 GMRES and of FP32 GMRES with the learned
     preconditioner on the same plane-wave right-hand side."""
     import numpy as np
@@ -193,7 +193,7 @@ def gmres_compare(fdb, synth, plan, tol: float, coupling: float, epochs: int, lo
     out = {"tol": tol}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x64, i64 = plan.solve(rhs, tol, maxit=200, restart=200, precond=0, raise_on_fail=False)
+    x64, i64 = plan.solve(rhs, tol, maxit=maxit, restart=maxit, precond=0, raise_on_fail=False)
     torch.cuda.synchronize()
     out["fp64_plain"] = {"iterations": i64["iterations"], "relres": i64["relres"], "status": i64["status"],
                          "seconds": time.perf_counter() - t0}
@@ -208,7 +208,7 @@ def gmres_compare(fdb, synth, plan, tol: float, coupling: float, epochs: int, lo
     for name, pc in (("fp32_block_jacobi", 1), ("fp32_learned", 2)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = plan.solve(rhs, tol, maxit=200, restart=200, precond=pc, fp32=True, raise_on_fail=False)
+        x, info = plan.solve(rhs, tol, maxit=maxit, restart=maxit, precond=pc, fp32=True, raise_on_fail=False)
         torch.cuda.synchronize()
         out[name] = {"iterations": info["iterations"], "relres": info["relres"], "status": info["status"],
                      "seconds": time.perf_counter() - t0,
@@ -533,6 +533,7 @@ def main() -> int:
     ap.add_argument("--cpu-rows", type=int, default=0)
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES time-to-tolerance comparison")
     ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--maxit", type=int, default=200, help="GMRES iteration limit (no restart below it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--coupling", type=float, default=-1.0,
@@ -670,7 +671,7 @@ def main() -> int:
     }
     if not args.no_solve and op == "BM_H":
         log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-        res["gmres"] = gmres_compare(fdb, synth, plan, 1e-4, args.coupling, args.epochs, log)
+        res["gmres"] = gmres_compare(fdb, synth, plan, 1e-4, args.coupling, args.epochs, log, args.maxit)
     free, total = torch.cuda.mem_get_info()
     res["peak_device_gb"] = max(peak_used, total - free) / 1e9
     res["plan_device_gb"] = plan.stats().get("device_bytes", 0) / 1e9
