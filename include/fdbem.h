@@ -114,6 +114,10 @@ typedef struct {
                            the uncompressed pseudo-inverses R+ and M2L matrices K (no
                            matrix reduction of section 4.1, no low-rank M2L of section
                            4.2); same results up to rounding, larger operators; 0 default */
+    int serial_slabs;   /* 0 (default): two scratch slabs of slab_mb each; every translation
+                           launch also sums the previous slab's per-pair results (same sums
+                           in the same order); 1: one slab, chunks and sums in separate
+                           launches                                                        */
 } fda_opts;
 
 typedef struct fda_plan fda_plan;

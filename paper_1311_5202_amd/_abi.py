@@ -43,7 +43,8 @@ class FdaOpts(ctypes.Structure):
                 ("autotune", ctypes.c_int),
                 ("slab_mb", ctypes.c_int),
                 ("hf_template", ctypes.c_int),
-                ("original", ctypes.c_int)]
+                ("original", ctypes.c_int),
+                ("serial_slabs", ctypes.c_int)]
 
 
 class FdaError(RuntimeError):

@@ -88,6 +88,7 @@ int fda_default_opts(fda_opts *o)
     o->slab_mb = 0;
     o->hf_template = 0;
     o->original = 0;
+    o->serial_slabs = 0;
     return FDA_OK;
 }
 
@@ -149,6 +150,7 @@ static Options parse_opts(const fda_opts *o)
         opt.hf_template = o->hf_template;
         if (o->original < 0 || o->original > 1) throw std::invalid_argument("original must be 0 or 1");
         opt.original = o->original;
+        opt.serial_slabs = o->serial_slabs ? 1 : 0;
     }
     if (opt.precision < FDA_PREC_FP64 || opt.precision > FDA_PREC_BOTH) throw std::invalid_argument("unknown precision");
     if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");

@@ -884,15 +884,13 @@ struct KSplit {
 };
 
 template <typename R, bool TRANS, int NT, int TAG>
-__global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, int s, int cols, int rmax,
-                                                                 const int64_t *__restrict__ ch_mat,
-                                                                 const int *__restrict__ ch_rank,
-                                                                 const int *__restrict__ ch_pptr,
-                                                                 const int64_t *__restrict__ pr_src,
-                                                                 const int64_t *__restrict__ pr_pos,
-                                                                 const typename Cx<R>::T *__restrict__ mat,
-                                                                 const typename Cx<R>::T *__restrict__ in,
-                                                                 typename Cx<R>::T *__restrict__ part)
+__device__ __forceinline__ void chunk_block(int bid, int n_chunks, int s, int cols, int rmax,
+                                            const int64_t *__restrict__ ch_mat, const int *__restrict__ ch_rank,
+                                            const int *__restrict__ ch_pptr, const int64_t *__restrict__ pr_src,
+                                            const int64_t *__restrict__ pr_pos,
+                                            const typename Cx<R>::T *__restrict__ mat,
+                                            const typename Cx<R>::T *__restrict__ in,
+                                            typename Cx<R>::T *__restrict__ part)
 {
     using C = typename Cx<R>::T;
     constexpr int PW = 16 * NT, PS = PW + 1;  // pairs per chunk, padded LDS row stride
@@ -903,7 +901,7 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
     // x takes the contiguous chunk range [x per, (x + 1) per); chunks of one
     // operator are adjacent and reuse that XCD's L2
     const int per = (n_chunks + kXcds - 1) / kXcds;
-    const int c = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int c = (bid % kXcds) * per + bid / kXcds;
     if (c >= n_chunks) return;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int p0 = ch_pptr[c], n = ch_pptr[c + 1] - p0;
@@ -973,17 +971,31 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, i
     }
 }
 
+template <typename R, bool TRANS, int NT, int TAG>
+__global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_mfma(int n_chunks, int s, int cols, int rmax,
+                                                                 const int64_t *__restrict__ ch_mat,
+                                                                 const int *__restrict__ ch_rank,
+                                                                 const int *__restrict__ ch_pptr,
+                                                                 const int64_t *__restrict__ pr_src,
+                                                                 const int64_t *__restrict__ pr_pos,
+                                                                 const typename Cx<R>::T *__restrict__ mat,
+                                                                 const typename Cx<R>::T *__restrict__ in,
+                                                                 typename Cx<R>::T *__restrict__ part)
+{
+    chunk_block<R, TRANS, NT, TAG>(blockIdx.x, n_chunks, s, cols, rmax, ch_mat, ch_rank, ch_pptr, pr_src, pr_pos, mat,
+                                   in, part);
+}
+
 // Sum of the per-pair results of each output slot (entries contiguous in
 // target-major order), one wavefront per output, lanes over rows; four
 // entries in flight per step, added in a fixed order.
-template <typename R, int TAG>
-__global__ __launch_bounds__(256) void k_seg_sum(int n_out, int s, const int64_t *__restrict__ red_out,
-                                                 const int64_t *__restrict__ red_ptr,
-                                                 const typename Cx<R>::T *__restrict__ part,
-                                                 typename Cx<R>::T *out)
+template <typename R>
+__device__ __forceinline__ void seg_sum_block(int bid, int n_out, int s, const int64_t *__restrict__ red_out,
+                                              const int64_t *__restrict__ red_ptr,
+                                              const typename Cx<R>::T *__restrict__ part, typename Cx<R>::T *out)
 {
     using C = typename Cx<R>::T;
-    const int o = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int o = bid * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (o >= n_out) return;
     const int64_t e0 = red_ptr[o], e1 = red_ptr[o + 1];
     C *dst = out + red_out[o];
@@ -1001,6 +1013,38 @@ __global__ __launch_bounds__(256) void k_seg_sum(int n_out, int s, const int64_t
         for (; e < e1; ++e, pp += s) a0 = cadd(a0, pp[0]);
         dst[row] = cadd(dst[row], cadd(cadd(a0, a1), cadd(a2, a3)));
     }
+}
+
+template <typename R, int TAG>
+__global__ __launch_bounds__(256) void k_seg_sum(int n_out, int s, const int64_t *__restrict__ red_out,
+                                                 const int64_t *__restrict__ red_ptr,
+                                                 const typename Cx<R>::T *__restrict__ part,
+                                                 typename Cx<R>::T *out)
+{
+    seg_sum_block<R>(blockIdx.x, n_out, s, red_out, red_ptr, part, out);
+}
+
+// One launch for two slabs of the partial-sum schedule: the first n_seg
+// workgroups sum the per-pair results of the previous slab (scratch buffer
+// prev) into its outputs while the others run the current slab's chunks into
+// the other scratch buffer, so the bandwidth-bound sums overlap the
+// latency-bound chunks and the launch tails.  n_seg is a multiple of the XCD
+// count, so the chunk workgroups keep their XCD-aware order.
+template <typename R, bool TRANS, int NT, int TAG>
+__global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_seg(
+    int n_seg, int n_out_prev, int s_prev, const int64_t *__restrict__ red_out_prev,
+    const int64_t *__restrict__ red_ptr_prev, const typename Cx<R>::T *__restrict__ prev,
+    typename Cx<R>::T *out_prev, int n_chunks, int s, int cols, int rmax, const int64_t *__restrict__ ch_mat,
+    const int *__restrict__ ch_rank, const int *__restrict__ ch_pptr, const int64_t *__restrict__ pr_src,
+    const int64_t *__restrict__ pr_pos, const typename Cx<R>::T *__restrict__ mat,
+    const typename Cx<R>::T *__restrict__ in, typename Cx<R>::T *__restrict__ part)
+{
+    if ((int)blockIdx.x < n_seg) {
+        seg_sum_block<R>(blockIdx.x, n_out_prev, s_prev, red_out_prev, red_ptr_prev, prev, out_prev);
+        return;
+    }
+    chunk_block<R, TRANS, NT, TAG>(blockIdx.x - n_seg, n_chunks, s, cols, rmax, ch_mat, ch_rank, ch_pptr, pr_src,
+                                   pr_pos, mat, in, part);
 }
 
 __global__ void k_corr(const int64_t *__restrict__ rp, const int32_t *__restrict__ blk,
@@ -1220,7 +1264,19 @@ static void set_mfma_lds(Device &D, size_t bytes)
                           (const void *)k_chunks_mfma<double, true, 2, TAG_L2L>,
                           (const void *)k_chunks_mfma<float, false, 2, TAG_M2L>,
                           (const void *)k_chunks_mfma<float, false, 2, TAG_M2M>,
-                          (const void *)k_chunks_mfma<float, true, 2, TAG_L2L>})
+                          (const void *)k_chunks_mfma<float, true, 2, TAG_L2L>,
+                          (const void *)k_chunks_seg<double, false, 1, TAG_M2L>,
+                          (const void *)k_chunks_seg<double, false, 1, TAG_M2M>,
+                          (const void *)k_chunks_seg<double, true, 1, TAG_L2L>,
+                          (const void *)k_chunks_seg<float, false, 1, TAG_M2L>,
+                          (const void *)k_chunks_seg<float, false, 1, TAG_M2M>,
+                          (const void *)k_chunks_seg<float, true, 1, TAG_L2L>,
+                          (const void *)k_chunks_seg<double, false, 2, TAG_M2L>,
+                          (const void *)k_chunks_seg<double, false, 2, TAG_M2M>,
+                          (const void *)k_chunks_seg<double, true, 2, TAG_L2L>,
+                          (const void *)k_chunks_seg<float, false, 2, TAG_M2L>,
+                          (const void *)k_chunks_seg<float, false, 2, TAG_M2M>,
+                          (const void *)k_chunks_seg<float, true, 2, TAG_L2L>})
         HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     have = bytes;
     D.mfma_lds = bytes;
@@ -1440,7 +1496,8 @@ void device_upload(Plan &P)
             if (mf > (size_t)maxsh) throw std::runtime_error("translation operator too large for LDS");
             set_mfma_lds(D, mf);
             D.part_bytes = part;
-            if (part) D.part = dalloc<double2>(D, part / sizeof(double2));
+            D.part_pipe = P.opt.serial_slabs == 0;
+            if (part) D.part = dalloc<double2>(D, (D.part_pipe ? 2 : 1) * part / sizeof(double2));
         }
         if (D.m2l_mode == 0) {
             build_m2l_chunks(P, M2LC_CH);
@@ -1692,6 +1749,69 @@ static void launch_slabs(const std::vector<DChunks> &S, void *part, const typena
     }
 }
 
+// Slabs in a pipeline over two scratch buffers: launch j runs the chunks of
+// slab j and the sums of slab j - 1 (k_chunks_seg); the sums of the last slab
+// stay pending in `pend` so that a caller can overlap them with the next
+// list's chunks when that list does not read their outputs (M2L levels), or
+// flush them (M2M and L2L levels).
+template <typename R>
+struct PendingSum {
+    const DChunks *c = nullptr;
+    void *part = nullptr;
+    typename Cx<R>::T *out = nullptr;
+};
+
+template <typename R, int TAG>
+static void flush_sum(PendingSum<R> &pend, hipStream_t st)
+{
+    using C = typename Cx<R>::T;
+    if (!pend.c) return;
+    const DChunks &c = *pend.c;
+    hipLaunchKernelGGL((k_seg_sum<R, TAG>), dim3((c.n_out + 3) / 4), dim3(256), 0, st, c.n_out, c.s, c.red_out,
+                       c.red_ptr, (const C *)pend.part, pend.out);
+    pend = PendingSum<R>();
+}
+
+template <int TAG, bool TRANS, typename R>
+static void launch_slabs_pipe(const std::vector<DChunks> &S, void *const part2[2], int &turn, PendingSum<R> &pend,
+                              const typename Cx<R>::T *mat, const typename Cx<R>::T *in, typename Cx<R>::T *out,
+                              hipStream_t st)
+{
+    using C = typename Cx<R>::T;
+    for (const DChunks &c : S) {
+        if (!c.n) continue;
+        void *part = part2[turn];
+        const size_t shm = mfma_shm(c) * sizeof(R) / sizeof(double);
+        const int chunk_grid = (int)(((c.n + kXcds - 1) / kXcds) * kXcds);
+        int n_seg = 0, n_out_prev = 0, s_prev = 0;
+        const int64_t *ro = nullptr, *rp = nullptr;
+        const C *prev = nullptr;
+        C *out_prev = nullptr;
+        if (pend.c) {
+            n_out_prev = pend.c->n_out;
+            s_prev = pend.c->s;
+            ro = pend.c->red_out;
+            rp = pend.c->red_ptr;
+            prev = (const C *)pend.part;
+            out_prev = pend.out;
+            n_seg = (int)((((n_out_prev + 3) / 4) + kXcds - 1) / kXcds * kXcds);
+        }
+        const dim3 grid((unsigned)(n_seg + chunk_grid)), block(64 * M2LC_WAVES);
+        if (c.pw == 32)
+            hipLaunchKernelGGL((k_chunks_seg<R, TRANS, 2, TAG>), grid, block, shm, st, n_seg, n_out_prev, s_prev, ro, rp,
+                               prev, out_prev, c.n, c.s, c.cols, c.rmax, c.ch_mat, c.ch_rank, c.ch_pptr, c.pr_src,
+                               c.pr_pos, mat, in, (C *)part);
+        else
+            hipLaunchKernelGGL((k_chunks_seg<R, TRANS, 1, TAG>), grid, block, shm, st, n_seg, n_out_prev, s_prev, ro, rp,
+                               prev, out_prev, c.n, c.s, c.cols, c.rmax, c.ch_mat, c.ch_rank, c.ch_pptr, c.pr_src,
+                               c.pr_pos, mat, in, (C *)part);
+        pend.c = &c;
+        pend.part = part;
+        pend.out = out;
+        turn ^= 1;
+    }
+}
+
 template <typename R, typename O>
 static void launch_s2m(Plan &P, Device &D, const O &c, const typename Cx<R>::T *tW, typename Cx<R>::T *od,
                        hipStream_t st)
@@ -1718,7 +1838,7 @@ static void launch_l2t(Plan &P, Device &D, const O &c, const typename Cx<R>::T *
 template <typename R, typename O>
 static void far_field_chunks(Plan &P, Device &D, const O &c, const typename Cx<R>::T *mat, const typename Cx<R>::T *tW,
                              const typename Cx<R>::T *tWt, typename Cx<R>::T *od, typename Cx<R>::T *id,
-                             void *part, hipEvent_t *ev, hipStream_t st)
+                             void *part, void *const *part2, hipEvent_t *ev, hipStream_t st)
 {
     using C = typename Cx<R>::T;
     if (D.n_od) hipLaunchKernelGGL(k_fill_zero<C>, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, od, D.n_od);
@@ -1726,22 +1846,35 @@ static void far_field_chunks(Plan &P, Device &D, const O &c, const typename Cx<R
     launch_s2m<R, O>(P, D, c, tW, od, st);
     if (ev) HIP_CHECK(hipEventRecord(ev[3], st));
     const bool slabs = D.m2l_mode == 3;
+    // two scratch buffers: pipelined slabs (the second buffer follows the first)
+    const bool pipe = slabs && part2 != nullptr;
+    int turn = 0;
+    PendingSum<R> pend;
     for (int l = D.n_lev - 2; l >= 0; --l) {
-        if (slabs)
+        if (pipe) {
+            launch_slabs_pipe<TAG_M2M, false, R>(D.m2ms[l], part2, turn, pend, mat, od, od, st);
+            flush_sum<R, TAG_M2M>(pend, st);  // the next level's M2M reads these outputs
+        } else if (slabs)
             launch_slabs<TAG_M2M, false, R>(D.m2ms[l], part, mat, od, od, st);
         else
             launch_chunks<TAG_M2M, false, R>(D.m2mc[l], D.m2mc[l].cols, mat, od, od, st);
     }
     if (ev) HIP_CHECK(hipEventRecord(ev[4], st));
     for (int l = 0; l < D.n_lev; ++l) {
-        if (slabs)
+        if (pipe)
+            launch_slabs_pipe<TAG_M2L, false, R>(D.m2ls[l], part2, turn, pend, mat, od, id, st);  // levels independent
+        else if (slabs)
             launch_slabs<TAG_M2L, false, R>(D.m2ls[l], part, mat, od, id, st);
         else
             launch_chunks<TAG_M2L, false, R>(D.m2lc[l], D.m2lc[l].s, mat, od, id, st);
     }
+    if (pipe) flush_sum<R, TAG_M2L>(pend, st);
     if (ev) HIP_CHECK(hipEventRecord(ev[5], st));
     for (int l = 1; l < D.n_lev; ++l) {
-        if (slabs)
+        if (pipe) {
+            launch_slabs_pipe<TAG_L2L, true, R>(D.l2ls[l], part2, turn, pend, mat, id, id, st);
+            flush_sum<R, TAG_L2L>(pend, st);  // the next level's L2L reads these outputs
+        } else if (slabs)
             launch_slabs<TAG_L2L, true, R>(D.l2ls[l], part, mat, id, id, st);
         else
             launch_chunks<TAG_L2L, true, R>(D.l2lc[l], D.l2lc[l].cols, mat, id, id, st);
@@ -1753,7 +1886,18 @@ static void far_field_chunks(Plan &P, Device &D, const O &c, const typename Cx<R
 void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st, void *part)
 {
     Device &D = *P.dev;
-    if (!part) part = D.part;
+    // the plan's scratch holds two slab buffers (pipelined slabs); a caller's
+    // buffer holds one unless it is twice the slab size
+    void *part2[2] = {nullptr, nullptr};
+    void *const *pp2 = nullptr;
+    if (!part) {
+        part = D.part;
+        if (D.part_pipe) {
+            part2[0] = D.part;
+            part2[1] = (char *)D.part + D.part_bytes;
+            pp2 = part2;
+        }
+    }
     const int64_t N = P.N;
     // low byte: operator; FDA_OP_FP32 (0x100) selects the FP32 far field and
     // near field on plans built with both precisions
@@ -1773,9 +1917,9 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
     if (P.opt.far_field && f32) {
         const OpCf cf = {make_float2((float)c.c0.x, (float)c.c0.y), make_float2((float)c.c1.x, (float)c.c1.y),
                          make_float2((float)c.d0.x, (float)c.d0.y), make_float2((float)c.d1.x, (float)c.d1.y)};
-        far_field_chunks<float, OpCf>(P, D, cf, D.matf, D.t_Wf, D.t_Wtf, D.odf, D.idf, part, ev, st);
+        far_field_chunks<float, OpCf>(P, D, cf, D.matf, D.t_Wf, D.t_Wtf, D.odf, D.idf, part, pp2, ev, st);
     } else if (P.opt.far_field && (D.m2l_mode == 0 || D.m2l_mode == 3)) {
-        far_field_chunks<double, OpC>(P, D, c, D.mat, D.t_W, D.t_Wt, D.od, D.id, part, ev, st);
+        far_field_chunks<double, OpC>(P, D, c, D.mat, D.t_W, D.t_Wt, D.od, D.id, part, pp2, ev, st);
     } else if (P.opt.far_field) {
         if (D.n_od) hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_od, 256)), dim3(256), 0, st, D.od, D.n_od);
         if (D.n_id) hipLaunchKernelGGL(k_fill_zero<double2>, dim3(nblk(D.n_id, 256)), dim3(256), 0, st, D.id, D.n_id);

@@ -101,6 +101,7 @@ struct Device {
     std::vector<std::vector<DChunks>> m2ls, m2ms, l2ls;
     void *part = nullptr;
     size_t part_bytes = 0;
+    bool part_pipe = false;            // part holds two slab buffers (pipelined slabs)
     void *static_part = nullptr;       // this device's copy of the static scratch
     int m2l_mode = 0;                  // 0 operator chunks, 1 per-target GEMV, 2 target tiles
     double2 *m2l_part = nullptr;       // partial sums of split tiles

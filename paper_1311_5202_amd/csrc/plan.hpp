@@ -36,6 +36,7 @@ struct Options {
                              // low-rank M2L (the paper's comparison method, Table 1)
     int autotune = 1;        // time the M2L/M2M/L2L chunk shapes on the plan and keep the faster
     int slab_mb = 1024;      // scratch of per-pair translation results per slab (MiB)
+    int serial_slabs = 0;    // 0: two slab buffers, each launch also sums the previous slab; 1: one buffer
     // k of the coupling: alpha = i / alpha_k()
     double alpha_k(double k) const { return k / coupling; }
 };
