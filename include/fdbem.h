@@ -260,9 +260,10 @@ void fda_batch_destroy(fda_batch *b);
  * (ne_b x 4) produced row by row by a small network (12 features of the pair
  * (b, j) -> 32 tanh -> 16 outputs: Re/Im of row j of U, then of W).
  * Training target: the restricted additive Schwarz rows R_b =
- * [(A|E_b)^{-1}]_{b,E_b}; loss = sum_b w_b ||[A_bb^{-1} 0] + U_b W_b^H -
+ * [(A|E_b)^{-1}]_{b,E_b}; loss = sum_b c_b w_b ||[A_bb^{-1} 0] + U_b W_b^H -
  * R_b||_F^2 with w_b = 1/||R_b - [A_bb^{-1} 0]||_F^2 (0 when that is at most
- * 1e-12 ||R_b||_F^2).  Features, forward, backward and Adam run on the GPU;
+ * 1e-12 ||R_b||_F^2) and c_b = 1 unless set from the method's own GMRES run
+ * by fda_net_weight_blocks.  Features, forward, backward and Adam run on the GPU;
  * the network lives on the device current at fda_net_create.  Every call is
  * synchronous. */
 typedef struct fda_net fda_net;
@@ -282,20 +283,28 @@ int fda_net_loss_grad(fda_net *net, fda_plan *plan, double *loss, double *grad);
 /* one Adam step (beta 0.9, 0.999) of learning rate lr > 0 on the plan's
  * blocks; *loss (may be NULL) is the loss before the step */
 int fda_net_train_step(fda_net *net, fda_plan *plan, double lr, double *loss);
+/* block weights c_b of the plan's training loss from the method's own GMRES
+ * run: `iters` steps of the block-Jacobi preconditioned solve of FDA_OP_BM_H
+ * with right-hand side rhs_dev (complex128[N] on the device), then c_b = the
+ * energy of its Krylov vectors (the directions its residuals take) on block
+ * b's overlapping set E_b, scaled to mean 1; iters = 0 restores c_b = 1.
+ * Needs a plan built with elements (FDA_EINVAL otherwise). */
+int fda_net_weight_blocks(fda_plan *plan, const void *rhs_dev, int iters);
 /* evaluate the network on the plan and load the factors for precond = 2;
  * net = NULL unloads them (precond = 2 then reports FDA_ENOTSUP) */
 int fda_net_attach(fda_net *net, fda_plan *plan);
 /* loss and gradient for caller data, all device pointers: per block b,
  * feature rows [pair_off[b], pair_off[b] + block_ne[b]) of the n_rows x 12
- * array (block points first), the inverse block at inv_off[b] (n_b x n_b) and
- * the target at target_off[b] (n_b x ne_b), column-major complex128.
+ * array (block points first), the inverse block at inv_off[b] (n_b x n_b),
+ * the target at target_off[b] (n_b x ne_b), column-major complex128, and the
+ * block weights c_b (n_blocks doubles, may be NULL for c_b = 1).
  * FDA_EINVAL unless 1 <= n_b <= 64, n_b <= ne_b <= 128 and the rows lie in
  * the array; the complex arrays must hold the blocks at their offsets.  For
  * checking the kernels against an independent implementation. */
 int fda_net_loss_grad_raw(fda_net *net, int n_blocks, const int64_t *pair_off, const int *block_n,
                           const int *block_ne, const int64_t *inv_off, const int64_t *target_off, int64_t n_rows,
-                          const double *features, const void *block_inv, const void *targets, double *loss,
-                          double *grad);
+                          const double *features, const void *block_inv, const void *targets,
+                          const double *block_weight, double *loss, double *grad);
 
 /* Release every device and host resource of the plan (NULL is allowed). */
 void fda_destroy(fda_plan *plan);

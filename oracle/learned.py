@@ -11,7 +11,8 @@ arrays and the chain rule, for checking them on synthetic inputs:
   rank-4 factor rows are U_jq = o_2q + i o_2q+1 (read for the block's own
   points) and W_jq = o_8+2q + i o_9+2q;
 * block loss: D_b = [B_b 0] + U_b W_b^H - R_b (n_b x ne_b, B_b the n_b x n_b
-  block inverse, R_b the target rows), L = sum_b w_b ||D_b||_F^2 with w_b =
+  block inverse, R_b the target rows), L = sum_b c_b w_b ||D_b||_F^2 (c_b an
+  optional weight per block, 1 by default) with w_b =
   1 / ||R_b - [B_b 0]||_F^2, or 0 when that is <= 1e-12 ||R_b||_F^2;
 * parameter vector: W1 (32 x 12, row-major), b1, W2 (16 x 32, row-major), b2.
 
@@ -71,26 +72,27 @@ def block_weight(B, R):
     return 1.0 / r if r > 1e-12 * t else 0.0
 
 
-def loss(theta, F, layout, Binv, T):
-    """layout = (poff, n, ne, inv_off, target_off), one entry per block."""
+def loss(theta, F, layout, Binv, T, c=None):
+    """layout = (poff, n, ne, inv_off, target_off), one entry per block; c:
+    optional extra weight per block (1 if None)."""
     _, _, U, W = forward(theta, F)
     total = 0.0
-    for p, n, ne, B, R in _blocks(layout, Binv, T):
+    for b, (p, n, ne, B, R) in enumerate(_blocks(layout, Binv, T)):
         D = B + U[p:p + n] @ W[p:p + ne].conj().T - R
-        total += block_weight(B, R) * np.sum(np.abs(D) ** 2)
+        total += (1.0 if c is None else c[b]) * block_weight(B, R) * np.sum(np.abs(D) ** 2)
     return total
 
 
-def loss_grad(theta, F, layout, Binv, T):
+def loss_grad(theta, F, layout, Binv, T, c=None):
     """(loss, gradient) by the chain rule written out."""
     W1, b1, W2, b2 = unpack(theta)
     Hh, _, U, W = forward(theta, F)
     dO = np.zeros((F.shape[0], NO))
     total = 0.0
-    for p, n, ne, B, R in _blocks(layout, Binv, T):
+    for b, (p, n, ne, B, R) in enumerate(_blocks(layout, Binv, T)):
         Ub, Wb = U[p:p + n], W[p:p + ne]
         D = B + Ub @ Wb.conj().T - R
-        wb = block_weight(B, R)
+        wb = (1.0 if c is None else c[b]) * block_weight(B, R)
         total += wb * np.sum(np.abs(D) ** 2)
         # |D_il|^2 with D_il = sum_q U_iq conj(W_lq) + ...:
         # d/dRe U_iq + i d/dIm U_iq = 2 (D W)_iq, likewise 2 (D^H U)_lq for W

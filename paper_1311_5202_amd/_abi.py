@@ -25,7 +25,7 @@ EXPORTS = ("fda_default_opts", "bem_nystrom_nodes", "bem_near_correction", "fda_
            "fda_stats", "fda_set_timing", "fda_phase_times", "fda_destroy", "fda_last_error", "fda_net_num_params",
            "fda_net_create", "fda_net_destroy", "fda_net_get_params", "fda_net_set_params", "fda_net_loss_grad",
            "fda_net_train_step", "fda_net_attach", "fda_net_loss_grad_raw", "fda_set_graph", "fda_batch_create",
-           "fda_batch_matvec", "fda_batch_solve", "fda_batch_destroy", "fda_rhs_neumann", "fda_matvec_noalloc", "fda_analyze")
+           "fda_batch_matvec", "fda_batch_solve", "fda_batch_destroy", "fda_rhs_neumann", "fda_matvec_noalloc", "fda_analyze", "fda_net_weight_blocks")
 
 
 class FdaGeometry(ctypes.Structure):
@@ -84,7 +84,8 @@ def lib() -> ctypes.CDLL:
     L.fda_net_loss_grad.argtypes = [vp, vp, ctypes.POINTER(dbl), vp]
     L.fda_net_train_step.argtypes = [vp, vp, dbl, ctypes.POINTER(dbl)]
     L.fda_net_attach.argtypes = [vp, vp]
-    L.fda_net_loss_grad_raw.argtypes = [vp, ci, vp, vp, vp, vp, vp, i64, vp, vp, vp, ctypes.POINTER(dbl), vp]
+    L.fda_net_loss_grad_raw.argtypes = [vp, ci, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]
+    L.fda_net_weight_blocks.argtypes = [vp, vp, ci]
     L.fda_set_graph.argtypes = [vp, ci]
     L.fda_batch_create.argtypes = [vp, ci, ctypes.POINTER(vp)]
     L.fda_batch_matvec.argtypes = [vp, ci, vp, vp, vp]

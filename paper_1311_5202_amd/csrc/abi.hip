@@ -499,10 +499,20 @@ int fda_net_attach(fda_net *net, fda_plan *plan)
     });
 }
 
+int fda_net_weight_blocks(fda_plan *plan, const void *rhs_dev, int iters)
+{
+    return guarded([&] {
+        if (!plan || (iters > 0 && !rhs_dev)) throw std::invalid_argument("null argument");
+        if (iters < 0 || iters > 1000) throw std::invalid_argument("iters must lie in [0, 1000]");
+        if (!plan->P->has_corr) throw std::invalid_argument("block weights need a plan built with elements");
+        return learned_weight_blocks(*plan->P, (const double2 *)rhs_dev, iters) >= 0 ? FDA_OK : FDA_EHIP;
+    });
+}
+
 int fda_net_loss_grad_raw(fda_net *net, int n_blocks, const int64_t *pair_off, const int *block_n,
                           const int *block_ne, const int64_t *inv_off, const int64_t *target_off, int64_t n_rows,
-                          const double *features, const void *block_inv, const void *targets, double *loss,
-                          double *grad)
+                          const double *features, const void *block_inv, const void *targets,
+                          const double *block_weight, double *loss, double *grad)
 {
     return guarded([&] {
         if (!net || !pair_off || !block_n || !block_ne || !inv_off || !target_off || !features || !block_inv ||
@@ -510,7 +520,7 @@ int fda_net_loss_grad_raw(fda_net *net, int n_blocks, const int64_t *pair_off, c
             throw std::invalid_argument("null argument");
         if (n_blocks <= 0 || n_rows <= 0) throw std::invalid_argument("empty problem");
         *loss = learned_loss_grad_raw(net->N, n_blocks, pair_off, block_n, block_ne, inv_off, target_off, n_rows,
-                                      features, (const double2 *)block_inv, (const double2 *)targets);
+                                      features, (const double2 *)block_inv, (const double2 *)targets, block_weight);
         if (grad) learned_get_grad(net->N, grad);
         return FDA_OK;
     });

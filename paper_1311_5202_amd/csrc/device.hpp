@@ -63,6 +63,8 @@ struct DLearn {
     double2 *T = nullptr;            // targets: column-major n x ne per block at toff
     int64_t *toff = nullptr;
     double *F = nullptr, *H = nullptr, *dout = nullptr, *loss = nullptr;
+    double *cw = nullptr;            // per-block weights from the method's GMRES runs (null: 1)
+    bool cw_active = false;
 };
 
 struct DLeaf {
@@ -153,6 +155,7 @@ void build_corrections_device(Plan &P, Device &D);
 void build_block_jacobi(Plan &P, Device &D);
 void apply_block_jacobi(Plan &P, const double2 *v, double2 *z, hipStream_t st, int mode);
 void learned_targets(Plan &P);
+int learned_weight_blocks(Plan &P, const double2 *rhs, int iters);
 
 struct LearnedNet;
 int learned_num_params();
@@ -167,7 +170,7 @@ void learned_attach(LearnedNet *N, Plan &P);
 void learned_detach(Plan &P);
 double learned_loss_grad_raw(LearnedNet *N, int nb, const int64_t *poff, const int *bsize, const int *bne,
                              const int64_t *boff, const int64_t *toff, int64_t n_rows, const double *F,
-                             const double2 *Binv, const double2 *T);
+                             const double2 *Binv, const double2 *T, const double *cw);
 void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t st, void *part = nullptr);
 // size of the file-scope scratch of the allocation-free mat-vec
 constexpr size_t kStaticScratchBytes = size_t(256) << 20;

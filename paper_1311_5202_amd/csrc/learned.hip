@@ -259,8 +259,8 @@ __global__ __launch_bounds__(EXT) void k_block_loss(const int64_t *__restrict__ 
                                                     const int *__restrict__ bne, const int64_t *__restrict__ boff,
                                                     const int64_t *__restrict__ toff,
                                                     const double2 *__restrict__ Binv, const double2 *__restrict__ T,
-                                                    const double *__restrict__ O, double *__restrict__ dout,
-                                                    double *__restrict__ loss)
+                                                    const double *__restrict__ O, const double *__restrict__ cw,
+                                                    double *__restrict__ dout, double *__restrict__ loss)
 {
     __shared__ double2 Ds[BMAX * EXT];
     __shared__ double red[EXT], red2[EXT], red3[EXT];
@@ -292,7 +292,8 @@ __global__ __launch_bounds__(EXT) void k_block_loss(const int64_t *__restrict__ 
         if (t < s) red[t] += red[t + s], red2[t] += red2[t + s], red3[t] += red3[t + s];
         __syncthreads();
     }
-    const double scale = red2[0] > 1e-12 * red3[0] ? 1.0 / red2[0] : 0.0;
+    // w_b, times the block's weight from the method's own GMRES runs when set
+    const double scale = (red2[0] > 1e-12 * red3[0] ? 1.0 / red2[0] : 0.0) * (cw ? cw[b] : 1.0);
     if (t == 0) loss[b] = red[0] * scale;
     if (t >= ne) return;
     double *o = dout + (r0 + t) * NO;
@@ -594,15 +595,16 @@ static void ensure_targets(Plan &P, Device &D)
 // forward, per-block loss, backward and gradient reduction; returns the summed loss
 static double loss_grad_core(LearnedNet *Nt, int nb, const int64_t *poff, const int *bsize, const int *bne,
                              const int64_t *boff, const int64_t *toff, int64_t rows, const double *F,
-                             const double2 *Binv, const double2 *T, double *H, double *O, double *dout, double *loss)
+                             const double2 *Binv, const double2 *T, const double *cw, double *H, double *O,
+                             double *dout, double *loss)
 {
     const int nblk = (int)std::min<int64_t>(lp::BW_GRID, (rows + lp::BWP - 1) / lp::BWP);
     double *partial = nullptr;
     HIP_CHECK(hipMalloc(&partial, sizeof(double) * (size_t)nblk * lp::NPAR));
     HIP_CHECK(hipMemset(dout, 0, sizeof(double) * rows * lp::NO));
     hipLaunchKernelGGL(lp::k_forward, dim3((unsigned)((rows + 127) / 128)), dim3(128), 0, 0, rows, F, Nt->th, H, O);
-    hipLaunchKernelGGL(lp::k_block_loss, dim3(nb), dim3(lp::EXT), 0, 0, poff, bsize, bne, boff, toff, Binv, T, O, dout,
-                       loss);
+    hipLaunchKernelGGL(lp::k_block_loss, dim3(nb), dim3(lp::EXT), 0, 0, poff, bsize, bne, boff, toff, Binv, T, O, cw,
+                       dout, loss);
     hipLaunchKernelGGL(lp::k_backward, dim3(nblk), dim3(lp::BWP), 0, 0, rows, F, H, Nt->th, dout, partial);
     hipLaunchKernelGGL(lp::k_grad_sum, dim3((lp::NPAR + 255) / 256), dim3(256), 0, 0, nblk, partial, Nt->grad);
     HIP_CHECK(hipGetLastError());
@@ -621,7 +623,7 @@ double learned_loss_grad(LearnedNet *Nt, Plan &P)
     ensure_targets(P, D);
     D.bj.rank = 0;  // the loss overwrites the loaded factors
     return loss_grad_core(Nt, D.bj.n_blocks, D.bj.poff, D.bj.size, D.bj.ne, D.bj.off, D.lt.toff, D.bj.n_pairs, D.lt.F,
-                          D.bj.inv, D.lt.T, D.lt.H, D.bj.O, D.lt.dout, D.lt.loss);
+                          D.bj.inv, D.lt.T, D.lt.cw, D.lt.H, D.bj.O, D.lt.dout, D.lt.loss);
 }
 
 void learned_get_grad(LearnedNet *N, double *g)
@@ -643,6 +645,74 @@ double learned_train_step(LearnedNet *Nt, Plan &P, double lr)
 // the exact restricted additive Schwarz rows (precond = 3)
 void learned_targets(Plan &P) { ensure_targets(P, *P.dev); }
 
+namespace lp {
+// energy of the Krylov vectors V_0 .. V_{nv-1} (caller order, length n) on the
+// overlapping set of each block: c_b = sum_j sum_{e in E_b} |V_j[e]|^2
+__global__ __launch_bounds__(EXT) void k_krylov_energy(int nv, int64_t n, const double2 *__restrict__ V,
+                                                       const int *__restrict__ bne, const int64_t *__restrict__ ext,
+                                                       double *__restrict__ c)
+{
+    __shared__ double red[EXT];
+    const int b = blockIdx.x, t = threadIdx.x;
+    double acc = 0.0;
+    if (t < bne[b]) {
+        const int64_t i = ext[(int64_t)b * EXT + t];
+        for (int j = 0; j < nv; ++j) {
+            const double2 v = V[(int64_t)j * n + i];
+            acc += v.x * v.x + v.y * v.y;
+        }
+    }
+    red[t] = acc;
+    __syncthreads();
+    for (int s = EXT / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    if (t == 0) c[b] = red[0];
+}
+}  // namespace lp
+
+// Block weights of the training loss from the method's own GMRES run: the
+// block-Jacobi preconditioned solve of the plan's Burton-Miller operator with
+// right-hand side rhs for `iters` steps; c_b is the energy of its Krylov
+// vectors (the directions its residuals take) on the block's overlapping set,
+// scaled to mean 1.  iters = 0 restores uniform weights.  Returns the number of
+// Krylov vectors used.
+int learned_weight_blocks(Plan &P, const double2 *rhs, int iters)
+{
+    Device &D = *P.dev;
+    ensure_targets(P, D);
+    const int nb = D.bj.n_blocks;
+    if (iters <= 0) {
+        if (D.lt.cw) HIP_CHECK(hipMemcpy(D.lt.cw, std::vector<double>(nb, 1.0).data(), 8 * (size_t)nb,
+                                         hipMemcpyHostToDevice));
+        D.lt.cw_active = false;
+        return 0;
+    }
+    double2 *x = nullptr;
+    HIP_CHECK(hipMalloc(&x, sizeof(double2) * P.N));
+    int it = 0;
+    double rel = 0;
+    // tolerance 0: the solve runs exactly `iters` steps unless it breaks down
+    device_gmres(P, 3, rhs, 1e-300, iters, iters, 1, x, &it, &rel, nullptr, 0);
+    HIP_CHECK(hipDeviceSynchronize());
+    (void)hipFree(x);
+    const int nv = std::max(1, std::min(it, D.gm_m));
+    if (!D.lt.cw) D.lt.cw = (double *)plan_alloc(D, 8 * (size_t)nb);
+    hipLaunchKernelGGL(lp::k_krylov_energy, dim3(nb), dim3(lp::EXT), 0, 0, nv, P.N, D.gm_V, D.bj.ne, D.bj.ext, D.lt.cw);
+    HIP_CHECK(hipGetLastError());
+    std::vector<double> c(nb);
+    HIP_CHECK(hipMemcpy(c.data(), D.lt.cw, 8 * (size_t)nb, hipMemcpyDeviceToHost));
+    double mean = 0;
+    for (double v : c) mean += v;
+    mean /= std::max(1, nb);
+    if (!(mean > 0) || !std::isfinite(mean)) throw std::runtime_error("no Krylov energy on the blocks");
+    for (double &v : c) v /= mean;
+    HIP_CHECK(hipMemcpy(D.lt.cw, c.data(), 8 * (size_t)nb, hipMemcpyHostToDevice));
+    D.lt.cw_active = true;
+    return nv;
+}
+
 // evaluate the network on a plan and keep its outputs for the preconditioner (precond = 2)
 void learned_attach(LearnedNet *Nt, Plan &P)
 {
@@ -662,7 +732,7 @@ void learned_detach(Plan &P) { P.dev->bj.rank = 0; }
 // at toff (n_b x ne_b), column-major complex
 double learned_loss_grad_raw(LearnedNet *Nt, int nb, const int64_t *poff, const int *bsize, const int *bne,
                              const int64_t *boff, const int64_t *toff, int64_t rows, const double *F,
-                             const double2 *Binv, const double2 *T)
+                             const double2 *Binv, const double2 *T, const double *cw)
 {
     {
         // the loss kernel holds one block in LDS: check the layout before any launch
@@ -686,7 +756,7 @@ double learned_loss_grad_raw(LearnedNet *Nt, int nb, const int64_t *poff, const 
     HIP_CHECK(hipMalloc(&loss, sizeof(double) * nb));
     double s = 0;
     try {
-        s = loss_grad_core(Nt, nb, poff, bsize, bne, boff, toff, rows, F, Binv, T, H, O, dout, loss);
+        s = loss_grad_core(Nt, nb, poff, bsize, bne, boff, toff, rows, F, Binv, T, cw, H, O, dout, loss);
     } catch (...) {
         for (void *p : {(void *)H, (void *)O, (void *)dout, (void *)loss}) (void)hipFree(p);
         throw;

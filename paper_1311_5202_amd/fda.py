@@ -319,16 +319,33 @@ class Net:
     def detach(plan: Plan):
         _abi.check(_abi.lib().fda_net_attach(None, plan._h))
 
-    def loss_grad_raw(self, pair_off, block_n, block_ne, inv_off, target_off, features, block_inv, targets):
+    @staticmethod
+    def weight_blocks(plan: Plan, rhs, iters: int):
+        """Block weights of the plan's training loss from `iters` steps of the
+        method's block-Jacobi GMRES on rhs (fda_net_weight_blocks); iters = 0
+        restores uniform weights."""
+        import torch
+
+        torch.cuda.synchronize()
+        ptr = None if rhs is None else ctypes.c_void_p(rhs.data_ptr())
+        _abi.check(_abi.lib().fda_net_weight_blocks(plan._h, ptr, int(iters)))
+
+    def loss_grad_raw(self, pair_off, block_n, block_ne, inv_off, target_off, features, block_inv, targets,
+                      block_weight=None):
         """Loss and gradient on caller data (fda_net_loss_grad_raw): CUDA
         tensors int64 pair_off, int32 block_n and block_ne, int64 inv_off and
         target_off, float64 features (rows x 12), complex128 block_inv and
         targets (column-major blocks at their offsets)."""
         import torch
 
-        for t, dt in ((pair_off, torch.int64), (block_n, torch.int32), (block_ne, torch.int32),
-                      (inv_off, torch.int64), (target_off, torch.int64), (features, torch.float64),
-                      (block_inv, torch.complex128), (targets, torch.complex128)):
+        checks = [(pair_off, torch.int64), (block_n, torch.int32), (block_ne, torch.int32),
+                  (inv_off, torch.int64), (target_off, torch.int64), (features, torch.float64),
+                  (block_inv, torch.complex128), (targets, torch.complex128)]
+        if block_weight is not None:
+            checks.append((block_weight, torch.float64))
+            if block_weight.numel() != pair_off.numel():
+                raise ValueError("one weight per block")
+        for t, dt in checks:
             if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
                 raise ValueError(f"expected a contiguous {dt} CUDA tensor")
         nb = pair_off.numel()
@@ -346,5 +363,6 @@ class Net:
         ptr = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
         _abi.check(_abi.lib().fda_net_loss_grad_raw(
             self._h, nb, ptr(pair_off), ptr(block_n), ptr(block_ne), ptr(inv_off), ptr(target_off),
-            features.shape[0], ptr(features), ptr(block_inv), ptr(targets), ctypes.byref(loss), g.ctypes.data))
+            features.shape[0], ptr(features), ptr(block_inv), ptr(targets),
+            None if block_weight is None else ptr(block_weight), ctypes.byref(loss), g.ctypes.data))
         return loss.value, g

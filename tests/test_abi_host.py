@@ -101,8 +101,11 @@ def test_launch_and_learned_entry_points_reject_null_arguments():
     assert L.fda_net_loss_grad(None, None, ctypes.byref(loss), None) == _abi.FDA_EINVAL
     assert L.fda_net_train_step(None, None, 1e-3, None) == _abi.FDA_EINVAL
     assert L.fda_net_attach(None, None) == _abi.FDA_EINVAL
-    assert L.fda_net_loss_grad_raw(None, 0, None, None, None, None, None, 0, None, None, None,
+    assert L.fda_net_loss_grad_raw(None, 0, None, None, None, None, None, 0, None, None, None, None,
                                    ctypes.byref(loss), None) == _abi.FDA_EINVAL
+    assert L.fda_net_weight_blocks(None, None, 3) == _abi.FDA_EINVAL
+    assert L.fda_rhs_neumann(None, None, None, None) == _abi.FDA_EINVAL
+    assert L.fda_matvec_noalloc(None, 3, None, None, None) == _abi.FDA_EINVAL
     L.fda_net_destroy(None)
     assert "null" in L.fda_last_error().decode() or L.fda_last_error()
 

@@ -22,11 +22,12 @@ def _dev(torch, a, dt):
     return torch.from_numpy(np.ascontiguousarray(a).astype(dt)).cuda()
 
 
-def _raw(torch, net, lay, B, T, F):
+def _raw(torch, net, lay, B, T, F, c=None):
     return net.loss_grad_raw(_dev(torch, lay[0], np.int64), _dev(torch, lay[1], np.int32),
                              _dev(torch, lay[2], np.int32), _dev(torch, lay[3], np.int64),
                              _dev(torch, lay[4], np.int64), _dev(torch, F, np.float64),
-                             _dev(torch, B, np.complex128), _dev(torch, T, np.complex128))
+                             _dev(torch, B, np.complex128), _dev(torch, T, np.complex128),
+                             None if c is None else _dev(torch, c, np.float64))
 
 
 def _plan(el, k, **kw):
@@ -58,6 +59,12 @@ def test_loss_and_gradient_match_oracle(torch, seed):
     # deterministic reduction: a second evaluation is bitwise identical
     L2, g2 = _raw(torch, net, lay, B, T, F)
     assert L2 == L and np.array_equal(g2, g)
+    # block weights (the GMRES-run weights of training)
+    c = np.random.default_rng(seed).uniform(0.0, 3.0, len(sizes))
+    Lc_ref, gc_ref = ol.loss_grad(th, F, lay, B, T, c)
+    Lc, gc = _raw(torch, net, lay, B, T, F, c)
+    assert Lc == pytest.approx(Lc_ref, rel=1e-12)
+    assert np.abs(gc - gc_ref).max() <= 1e-11 * np.abs(gc_ref).max()
 
 
 def test_raw_layout_is_checked(torch):
@@ -112,6 +119,27 @@ def test_block_jacobi_and_learned_solves(torch):
     fdb.Net.detach(test_plan)
     _, info = test_plan.solve(rhs, 1e-6, maxit=10, restart=10, precond=2, raise_on_fail=False)
     assert info["status"] == _abi.FDA_ENOTSUP
+
+    # training data from the method's own GMRES runs: block weights from the
+    # Krylov vectors of 20 block-Jacobi steps on each training surface
+    L_plain = net.loss_grad(train[0])[0]
+    for s_, p in enumerate(train):
+        fdb.Net.weight_blocks(p, p.rhs_plane_wave(synth.random_directions(1, 50 + s_)[0]), 20)
+    L_weighted = net.loss_grad(train[0])[0]
+    fdb.Net.weight_blocks(train[0], None, 0)
+    assert net.loss_grad(train[0])[0] == L_plain  # uniform weights restored exactly
+    fdb.Net.weight_blocks(train[0], train[0].rhs_plane_wave(synth.random_directions(1, 50)[0]), 20)
+    assert net.loss_grad(train[0])[0] == L_weighted  # the same run gives the same weights
+    net_k = fdb.Net(7)
+    for _ in range(300):
+        for p in train:
+            net_k.train_step(p, 3e-3)
+    net_k.attach(test_plan)
+    xk, ik = test_plan.solve(rhs, 1e-6, maxit=300, restart=300, precond=2)
+    print(f"[learned] trained with GMRES-run block weights: {ik['iterations']} iterations "
+          f"(uniform weights {i2['iterations']}, block-Jacobi {i1['iterations']})", flush=True)
+    assert rel(xk) < 1e-5 and ik["iterations"] <= 0.8 * i1["iterations"]
+    net_k.close()
 
 
 def test_plan_gradient_matches_differences(torch):

@@ -91,3 +91,26 @@ def test_closed_form_losses():
         exp += 2 * w * (Bb - Rb).sum()
     assert g[o2] == pytest.approx(exp.real, rel=1e-12)
     assert g[o2 + 1] == pytest.approx(exp.imag, rel=1e-12)
+
+
+def test_block_weights_scale_each_block():
+    """Extra block weights c_b scale each block's term: the weighted loss is
+    the sum of single-block losses times c_b (each computed without weights
+    on a layout holding that block alone), and the weighted gradient matches
+    central differences of the weighted loss."""
+    sizes, extras = [5, 9, 1, 17], [3, 0, 7, 40]
+    lay, B, T, F = synth.learned_blocks(4, sizes, extras)
+    th = ol.random_theta(8)
+    c = np.array([0.5, 2.0, 0.0, 1.7])
+    L, g = ol.loss_grad(th, F, lay, B, T, c)
+    parts = []
+    for b in range(len(sizes)):
+        one = tuple(np.asarray(v)[b:b + 1] for v in lay)
+        parts.append(ol.loss(th, F, one, B, T))
+    assert L == pytest.approx(float(np.dot(c, parts)), rel=1e-12)
+    h = 1e-6
+    for i in (0, 17, ol.NPAR - 1, ol.NF * ol.NH + 3):
+        e = np.zeros(ol.NPAR)
+        e[i] = h
+        fd = (ol.loss(th + e, F, lay, B, T, c) - ol.loss(th - e, F, lay, B, T, c)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i]))
