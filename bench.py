@@ -53,7 +53,12 @@ WORKLOADS = {
     "c1": (8, 5.0, 1e-4, "unit sphere, 512 quadratic triangles, N=3072, k=5 (kD=10), eps=1e-4"),
     "c2": (64, 50.0, 1e-4, "unit sphere, 32768 quadratic triangles, N=196608, k=50 (kD=100), eps=1e-4, leaf<=64"),
     "c5": (289, 500.0, 1e-4, "unit sphere, 668168 quadratic triangles, N=4009008, k=500 (kD=1000), eps=1e-4"),
+    # elongated body standing in for the paper's large non-spherical model: a
+    # 1:1:8 prolate ellipsoid (D = 16) at kD = 1000; raw H sum (no elements)
+    "f4": (192, 62.5, 1e-4, "prolate ellipsoid 1:1:8 (D=16), 294912 quadratic triangles, N=1769472, "
+                            "k=62.5 (kD=1000), eps=1e-4, raw H sum"),
 }
+ELONGATED = {"f4": 8.0}
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
@@ -594,12 +599,13 @@ def main() -> int:
     if args.workload in TABLE1:
         return table1_main(args, fdb, synth, torch)
     n_split, k, eps, desc = WORKLOADS[args.workload]
-    el = synth.octa_sphere(n_split)
+    aspect = ELONGATED.get(args.workload)
+    el = synth.octa_sphere(n_split) if aspect is None else synth.ellipsoid(n_split, aspect)
     pts, nrm, w = fdb.nystrom_nodes(el)
     N = len(w)
     t0 = time.perf_counter()
-    plan = fdb.build(pts, nrm, w, k, eps, elements=el, corrections=1, verbose=1, precision="both",
-                     coupling=args.coupling)
+    plan = fdb.build(pts, nrm, w, k, eps, elements=el if aspect is None else None, corrections=1, verbose=1,
+                     precision="both", coupling=args.coupling)
     t_build = time.perf_counter() - t0
     st = plan.stats()
     print(f"[bench] workload={args.workload} N={N} k={k} p2p_pairs={st['p2p_pairs']} build {t_build:.1f} s m2l_tile={st.get('m2l_tile')} tiles(t,ch,p,seg)={st.get('m2l_tiles')} lds={st.get('m2l_lds_bytes')}/{st.get('max_lds_per_block')}", file=sys.stderr, flush=True)
