@@ -86,19 +86,25 @@ def m2l_work(plan_stats: dict) -> tuple[float, float]:
 
 def phase_rooflines(st: dict, phases: dict) -> dict:
     """Achieved rates of the other far-field phases against the peak that
-    bounds them: M2M and L2L stream slots and small dense operators (HBM,
-    minimum bytes: unique operators, input and output slots once); S2M and
-    L2T evaluate kernels between leaf points and check points and apply W
-    (FP64 vector ALU)."""
+    bounds them: M2M and L2L apply small dense operators to slots (matrix
+    cores when their flops per minimum byte -- unique operators, input and
+    output slots once -- exceed the machine balance, else HBM); S2M and L2T
+    evaluate kernels between leaf points and check points and apply W (FP64
+    vector ALU)."""
     out = {}
     for name in ("m2m", "l2l"):
         byts = sum(L[f"{name}_min_bytes"] for L in st["levels"])
         flops = sum(L[f"{name}_flops"] for L in st["levels"])
         ms = phases[name]
         gbs = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        out[name] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": gbs / PEAK_HBM_GBS, "algorithmic_bytes": byts, "flops": flops,
-                     "tflops": flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0}
+        tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        # bound by arithmetic intensity against the machine balance (flop per byte)
+        if byts > 0 and flops / byts > PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9):
+            out[name] = {"bound": "mfma", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / PEAK_FP64_TFLOPS, "algorithmic_bytes": byts, "flops": flops, "gbs": gbs}
+        else:
+            out[name] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": gbs / PEAK_HBM_GBS, "algorithmic_bytes": byts, "flops": flops, "tflops": tf}
     for name in ("s2m", "l2t"):
         flops = EVAL_FLOPS * st[f"{name}_evals"] + st[f"{name}_w_flops"]
         ms = phases[name]

@@ -1381,9 +1381,10 @@ void device_upload(Plan &P)
     }
     D.n_leaf = (int)P.leaves.size();
     {
-        // target leaves in decreasing order of P2P work (one wavefront each:
-        // per block of 64 targets, the source steps of 64/nt slices), so the
-        // longest wavefronts start first and the short ones fill the tail
+        // target leaves: the heaviest 2% by P2P work first, in decreasing order
+        // (one wavefront each: per block of 64 targets, the source steps of
+        // 64/nt slices), so the longest wavefronts do not end up in the tail;
+        // the rest in tree order, where neighbouring leaves share sources in L2
         const int nl = (int)P.p2p_tgt_start.size();
         std::vector<double> work(nl, 0.0);
         for (int t = 0; t < nl; ++t) {
@@ -1397,6 +1398,14 @@ void device_upload(Plan &P)
         std::vector<int> order(nl);
         for (int t = 0; t < nl; ++t) order[t] = t;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+        {
+            const int heavy = nl / 50;
+            std::vector<char> first(nl, 0);
+            for (int q = 0; q < heavy; ++q) first[order[q]] = 1;
+            int q = heavy;
+            for (int t = 0; t < nl; ++t)
+                if (!first[t]) order[q++] = t;
+        }
         std::vector<int64_t> ts(nl), te(nl), ss, se;
         std::vector<int> ptr(nl + 1, 0);
         ss.reserve(P.p2p_src_start.size());
