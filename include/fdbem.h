@@ -101,8 +101,9 @@ typedef struct {
                            eq. eq_bm); 0 -> 1, the value the paper uses.  -1 gives the
                            conjugate coupling (see bm_solve). */
     int autotune;       /* 1 (default): at build, time 16 and 32 pairs per M2L, M2M and L2L
-                           chunk on the plan's own lists and keep the faster per translation
-                           and level (fda_stats: m2l_/m2m_/l2l_autotune); 0: 16 */
+                           chunk of the workgroup kernel on the plan's own lists and keep the
+                           faster per translation and level (fda_stats: m2l_/m2m_/l2l_autotune;
+                           levels on the wavefront kernel are timed, not tuned); 0: 16 */
     int slab_mb;        /* scratch for per-pair translation results, MiB per slab; 0 -> 1024 */
     int hf_template;    /* high-frequency templates: 0 (default) one per wedge orbit, check
                            points on the region where the wedge's outgoing field is evaluated
@@ -118,6 +119,12 @@ typedef struct {
                            launch also sums the previous slab's per-pair results (same sums
                            in the same order); 1: one slab, chunks and sums in separate
                            launches                                                        */
+    int chunk_kernel;   /* translation chunks of the default schedule: 0 (default) one
+                           wavefront per chunk for every translation list (one kind and
+                           level) whose operators all fit it (dense, or low-rank with rank
+                           at most 32), the workgroup kernel for the
+                           other lists; 1: the workgroup kernel everywhere.  Results of the
+                           two kernels differ by rounding only; neither depends on slab_mb. */
 } fda_opts;
 
 typedef struct fda_plan fda_plan;

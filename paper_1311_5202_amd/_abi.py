@@ -44,7 +44,8 @@ class FdaOpts(ctypes.Structure):
                 ("slab_mb", ctypes.c_int),
                 ("hf_template", ctypes.c_int),
                 ("original", ctypes.c_int),
-                ("serial_slabs", ctypes.c_int)]
+                ("serial_slabs", ctypes.c_int),
+                ("chunk_kernel", ctypes.c_int)]
 
 
 class FdaError(RuntimeError):

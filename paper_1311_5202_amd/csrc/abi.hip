@@ -89,6 +89,7 @@ int fda_default_opts(fda_opts *o)
     o->hf_template = 0;
     o->original = 0;
     o->serial_slabs = 0;
+    o->chunk_kernel = 0;
     return FDA_OK;
 }
 
@@ -151,6 +152,8 @@ static Options parse_opts(const fda_opts *o)
         if (o->original < 0 || o->original > 1) throw std::invalid_argument("original must be 0 or 1");
         opt.original = o->original;
         opt.serial_slabs = o->serial_slabs ? 1 : 0;
+        if (o->chunk_kernel < 0 || o->chunk_kernel > 1) throw std::invalid_argument("chunk_kernel must be 0 or 1");
+        opt.chunk_kernel = o->chunk_kernel;
     }
     if (opt.precision < FDA_PREC_FP64 || opt.precision > FDA_PREC_BOTH) throw std::invalid_argument("unknown precision");
     if (opt.leaf_rule != 0) throw std::invalid_argument("unknown leaf rule");
@@ -299,10 +302,12 @@ int fda_stats(const fda_plan *plan, char *buf, size_t len)
                 bool first = true;
                 for (const auto &a : P.dev->autotune) {
                     if ((int)a[4] != kind) continue;
-                    char buf[160];
+                    char buf[200];
                     std::snprintf(buf, sizeof buf,
-                                  "%s{\"level\": %d, \"pairs_per_chunk\": %d, \"ms_16\": %.4f, \"ms_32\": %.4f}",
-                                  first ? "" : ", ", (int)a[0], (int)a[1], a[2], a[3] < 1e29 ? a[3] : -1.0);
+                                  "%s{\"level\": %d, \"pairs_per_chunk\": %d, \"ms_16\": %.4f, \"ms_32\": %.4f, "
+                                  "\"kernel\": \"%s\"}",
+                                  first ? "" : ", ", (int)a[0], (int)a[1], a[2], a[3] < 1e29 ? a[3] : -1.0,
+                                  a[5] > 0 ? "wavefront" : "workgroup");
                     s += buf;
                     first = false;
                 }

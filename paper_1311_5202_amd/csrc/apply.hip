@@ -770,6 +770,8 @@ struct Mf<double> {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int out_row(int q, int k4) { return 4 * q + k4; }
+    // tile row computed by A row m so that result register q of lane group k4 is row 4 k4 + q
+    static __device__ __forceinline__ int rho(int m) { return 4 * (m & 3) + (m >> 2); }
 };
 template <>
 struct Mf<float> {
@@ -779,6 +781,7 @@ struct Mf<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int out_row(int q, int k4) { return 4 * k4 + q; }
+    static __device__ __forceinline__ int rho(int m) { return m; }
 };
 
 // one real-GEMM sweep over the row tiles: complex A has rows [0, nrow) and
@@ -1047,6 +1050,356 @@ __global__ __launch_bounds__(64 * M2LC_WAVES) void k_chunks_seg(
                                    pr_pos, mat, in, part);
 }
 
+// Translation chunks, one wavefront per chunk of <= 16 pairs sharing one
+// operator (four chunks per workgroup): no LDS and no barrier.  The operator
+// comes from a row-major copy of the pool: dense A (s x cols), or U (s x r)
+// followed by V (r x cols) of a low-rank one.  Real inner index k of four
+// consecutive matrix-core steps (g, t) is 16 g + 4 k4 + t for lane group k4,
+// so that a lane reads two adjacent complex entries of an operator row or of
+// its source vector per four steps.  The A row that each lane supplies is
+// permuted by Mf::rho, so that result register q of lane group k4 holds real
+// row 4 k4 + q of the tile: for a low-rank operator the result T = V X is then
+// already the B operand of Y = U T (register q of T tile g is step (g, q)),
+// and a lane stores two adjacent complex rows of Y.
+constexpr int WV_GMAX = 8;   // dense operators of at most 64 columns hold the sources in registers
+constexpr int WV_RMAX = 32;  // low-rank operators: rank at most 32
+
+// Four A values of lane row I (real row of the product) at the inner group
+// starting at complex column j0: entries (i, j0) and (i, j0 + 1) of the
+// row-major complex matrix M (nrow x ncol), zero outside it.
+template <typename R>
+__device__ __forceinline__ void wv_a(const typename Cx<R>::T *__restrict__ M, int nrow, int ncol, int I, int j0,
+                                     R a[4])
+{
+    using C = typename Cx<R>::T;
+    const int i = I >> 1;
+    const bool im = I & 1, rok = i < nrow, ok0 = rok && j0 < ncol, ok1 = rok && j0 + 1 < ncol;
+    const C *p = M + (int64_t)(rok ? i : 0) * ncol;
+    const C m0 = p[ok0 ? j0 : 0], m1 = p[ok1 ? j0 + 1 : 0];
+    const R r0 = ok0 ? m0.x : (R)0, i0 = ok0 ? m0.y : (R)0, r1 = ok1 ? m1.x : (R)0, i1 = ok1 ? m1.y : (R)0;
+    // row (Re, Im) of y_i against inner (Re, Im) of x_j: [Re -Im; Im Re]
+    a[0] = im ? i0 : r0;
+    a[1] = im ? r0 : -i0;
+    a[2] = im ? i1 : r1;
+    a[3] = im ? r1 : -i1;
+}
+
+// Four B values: (Re, Im) of entries j0 and j0 + 1 of a source vector
+template <typename R>
+__device__ __forceinline__ void wv_b(const typename Cx<R>::T *__restrict__ x, int ncol, int j0, bool pok, R b[4])
+{
+    using C = typename Cx<R>::T;
+    const bool ok0 = pok && j0 < ncol, ok1 = pok && j0 + 1 < ncol;
+    const C x0 = x[ok0 ? j0 : 0], x1 = x[ok1 ? j0 + 1 : 0];
+    b[0] = ok0 ? x0.x : (R)0;
+    b[1] = ok0 ? x0.y : (R)0;
+    b[2] = ok1 ? x1.x : (R)0;
+    b[3] = ok1 ? x1.y : (R)0;
+}
+
+// Complex rows 8 rt + 2 k4 and the next of a result tile to the pair's scratch row
+template <typename R>
+__device__ __forceinline__ void wv_store(typename Cx<R>::T *dst, bool ok, int s, int rt, int k4,
+                                         const typename Mf<R>::V &y)
+{
+    const int m0 = 8 * rt + 2 * k4;
+    if (ok && m0 < s) dst[m0] = Cx<R>::mk(y[0], y[1]);
+    if (ok && m0 + 1 < s) dst[m0 + 1] = Cx<R>::mk(y[2], y[3]);
+}
+
+// Y = A X for a dense operator, cols <= 64: the source groups stay in
+// registers and the row tiles go two at a time (two independent chains)
+template <typename R>
+__device__ __forceinline__ void wv_dense(const typename Cx<R>::T *__restrict__ A, int s, int cols,
+                                         const typename Cx<R>::T *__restrict__ x, bool pok,
+                                         typename Cx<R>::T *dst, int i16, int k4)
+{
+    typedef typename Mf<R>::V V;
+    const int G = (2 * cols + 15) >> 4, n_rt = (2 * s + 15) >> 4, rw = Mf<R>::rho(i16);
+    R xb[WV_GMAX][4];
+#pragma unroll
+    for (int g = 0; g < WV_GMAX; ++g) {
+        if (g < G) {
+            wv_b<R>(x, cols, 8 * g + 2 * k4, pok, xb[g]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) xb[g][t] = (R)0;
+        }
+    }
+    int rt = 0;
+    for (; rt + 1 < n_rt; rt += 2) {
+        V y0 = {0, 0, 0, 0}, y1 = y0;
+#pragma unroll
+        for (int g = 0; g < WV_GMAX; ++g) {
+            if (g < G) {
+                R a0[4], a1[4];
+                wv_a<R>(A, s, cols, 16 * rt + rw, 8 * g + 2 * k4, a0);
+                wv_a<R>(A, s, cols, 16 * rt + 16 + rw, 8 * g + 2 * k4, a1);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    y0 = Mf<R>::mma(a0[t], xb[g][t], y0);
+                    y1 = Mf<R>::mma(a1[t], xb[g][t], y1);
+                }
+            }
+        }
+        wv_store<R>(dst, pok, s, rt, k4, y0);
+        wv_store<R>(dst, pok, s, rt + 1, k4, y1);
+    }
+    if (rt < n_rt) {
+        V y0 = {0, 0, 0, 0};
+#pragma unroll
+        for (int g = 0; g < WV_GMAX; ++g) {
+            if (g < G) {
+                R a0[4];
+                wv_a<R>(A, s, cols, 16 * rt + rw, 8 * g + 2 * k4, a0);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) y0 = Mf<R>::mma(a0[t], xb[g][t], y0);
+            }
+        }
+        wv_store<R>(dst, pok, s, rt, k4, y0);
+    }
+}
+
+// Y = A X for a dense operator of any width: the source groups are read
+// again for every pair of row tiles (same products in the same order as
+// wv_dense, so the same result bit for bit)
+template <typename R>
+__device__ __forceinline__ void wv_dense_stream(const typename Cx<R>::T *__restrict__ A, int s, int cols,
+                                                const typename Cx<R>::T *__restrict__ x, bool pok,
+                                                typename Cx<R>::T *dst, int i16, int k4)
+{
+    typedef typename Mf<R>::V V;
+    const int G = (2 * cols + 15) >> 4, n_rt = (2 * s + 15) >> 4, rw = Mf<R>::rho(i16);
+    int rt = 0;
+    for (; rt + 1 < n_rt; rt += 2) {
+        V y0 = {0, 0, 0, 0}, y1 = y0;
+        for (int g = 0; g < G; ++g) {
+            R a0[4], a1[4], xb[4];
+            wv_b<R>(x, cols, 8 * g + 2 * k4, pok, xb);
+            wv_a<R>(A, s, cols, 16 * rt + rw, 8 * g + 2 * k4, a0);
+            wv_a<R>(A, s, cols, 16 * rt + 16 + rw, 8 * g + 2 * k4, a1);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                y0 = Mf<R>::mma(a0[t], xb[t], y0);
+                y1 = Mf<R>::mma(a1[t], xb[t], y1);
+            }
+        }
+        wv_store<R>(dst, pok, s, rt, k4, y0);
+        wv_store<R>(dst, pok, s, rt + 1, k4, y1);
+    }
+    if (rt < n_rt) {
+        V y0 = {0, 0, 0, 0};
+        for (int g = 0; g < G; ++g) {
+            R a0[4], xb[4];
+            wv_b<R>(x, cols, 8 * g + 2 * k4, pok, xb);
+            wv_a<R>(A, s, cols, 16 * rt + rw, 8 * g + 2 * k4, a0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) y0 = Mf<R>::mma(a0[t], xb[t], y0);
+        }
+        wv_store<R>(dst, pok, s, rt, k4, y0);
+    }
+}
+
+// Y = U (V X) for a low-rank operator with 2 r <= 16 RT rows of T, on NP
+// tiles of 16 pairs (every operator value loaded feeds NP products; a pair's
+// result does not depend on NP bit for bit)
+template <typename R, int RT, int NP>
+__device__ __forceinline__ void wv_lowrank(const typename Cx<R>::T *__restrict__ M, int s, int cols, int r,
+                                           const typename Cx<R>::T *const x[NP], const bool pok[NP],
+                                           typename Cx<R>::T *const dst[NP], int i16, int k4)
+{
+    typedef typename Mf<R>::V V;
+    const typename Cx<R>::T *U = M, *Vm = M + (int64_t)s * r;
+    const int G = (2 * cols + 15) >> 4, n_rt = (2 * s + 15) >> 4, rw = Mf<R>::rho(i16);
+    // T = V X; with one tile of T, even and odd inner groups go to two
+    // partial sums (independent chains), added in a fixed order at the end
+    constexpr bool two = RT == 1;
+    V t[RT][NP], t2[RT][NP];
+#pragma unroll
+    for (int q = 0; q < RT; ++q)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) t[q][p] = t2[q][p] = V{0, 0, 0, 0};
+    int g = 0;
+    for (; g + 1 < G; g += 2) {
+        R b0[NP][4], b1[NP][4];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            wv_b<R>(x[p], cols, 8 * g + 2 * k4, pok[p], b0[p]);
+            wv_b<R>(x[p], cols, 8 * g + 8 + 2 * k4, pok[p], b1[p]);
+        }
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            R a0[4], a1[4];
+            wv_a<R>(Vm, r, cols, 16 * q + rw, 8 * g + 2 * k4, a0);
+            wv_a<R>(Vm, r, cols, 16 * q + rw, 8 * g + 8 + 2 * k4, a1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) t[q][p] = Mf<R>::mma(a0[u], b0[p][u], t[q][p]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    if (two)
+                        t2[q][p] = Mf<R>::mma(a1[u], b1[p][u], t2[q][p]);
+                    else
+                        t[q][p] = Mf<R>::mma(a1[u], b1[p][u], t[q][p]);
+                }
+        }
+    }
+    if (g < G) {
+        R b0[NP][4];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) wv_b<R>(x[p], cols, 8 * g + 2 * k4, pok[p], b0[p]);
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            R a0[4];
+            wv_a<R>(Vm, r, cols, 16 * q + rw, 8 * g + 2 * k4, a0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) t[q][p] = Mf<R>::mma(a0[u], b0[p][u], t[q][p]);
+        }
+    }
+    if (two) {
+#pragma unroll
+        for (int q = 0; q < RT; ++q)
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) t[q][p][e] += t2[q][p][e];
+    }
+    // Y = U T, two row tiles at a time
+    int rt = 0;
+    for (; rt + 1 < n_rt; rt += 2) {
+        V y0[NP], y1[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) y0[p] = y1[p] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            R a0[4], a1[4];
+            wv_a<R>(U, s, r, 16 * rt + rw, 8 * q + 2 * k4, a0);
+            wv_a<R>(U, s, r, 16 * rt + 16 + rw, 8 * q + 2 * k4, a1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    y0[p] = Mf<R>::mma(a0[u], t[q][p][u], y0[p]);
+                    y1[p] = Mf<R>::mma(a1[u], t[q][p][u], y1[p]);
+                }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            wv_store<R>(dst[p], pok[p], s, rt, k4, y0[p]);
+            wv_store<R>(dst[p], pok[p], s, rt + 1, k4, y1[p]);
+        }
+    }
+    if (rt < n_rt) {
+        V y0[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) y0[p] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < RT; ++q) {
+            R a0[4];
+            wv_a<R>(U, s, r, 16 * rt + rw, 8 * q + 2 * k4, a0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) y0[p] = Mf<R>::mma(a0[u], t[q][p][u], y0[p]);
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) wv_store<R>(dst[p], pok[p], s, rt, k4, y0[p]);
+    }
+}
+
+// One launch of the wavefront chunks, the first n_seg workgroups summing the
+// previous slab's per-pair results as in k_chunks_seg (n_seg = 0: none).
+// Chunk workgroups are dealt to the XCDs in contiguous ranges.  KIND names
+// the operators a slab holds, so that an instance keeps only the registers
+// its paths need: 0 dense, 1 low-rank of rank <= 16, 2 low-rank, 3 both, 4
+// both with dense operators of more than 64 columns.
+// NP: tiles of 16 pairs per chunk (2 only for low-rank slabs).
+template <typename R, int TAG, int KIND, int NP>
+__global__ __launch_bounds__(256) void k_wave_seg(
+    int n_seg, int n_out_prev, int s_prev, const int64_t *__restrict__ red_out_prev,
+    const int64_t *__restrict__ red_ptr_prev, const typename Cx<R>::T *__restrict__ prev,
+    typename Cx<R>::T *out_prev, int n_chunks, int s, int cols, const int64_t *__restrict__ ch_mat,
+    const int *__restrict__ ch_rank, const int *__restrict__ ch_pptr, const int64_t *__restrict__ pr_src,
+    const int64_t *__restrict__ pr_pos, const typename Cx<R>::T *__restrict__ mat,
+    const typename Cx<R>::T *__restrict__ in, typename Cx<R>::T *__restrict__ part)
+{
+    using C = typename Cx<R>::T;
+    static_assert(NP == 1 || (KIND == 1 || KIND == 2), "two pair tiles only for low-rank slabs");
+    if ((int)blockIdx.x < n_seg) {
+        seg_sum_block<R>(blockIdx.x, n_out_prev, s_prev, red_out_prev, red_ptr_prev, prev, out_prev);
+        return;
+    }
+    const int b = (int)blockIdx.x - n_seg, nb = (n_chunks + 3) >> 2, per = (nb + kXcds - 1) / kXcds;
+    const int c = 4 * ((b % kXcds) * per + b / kXcds) + (int)(threadIdx.x >> 6);
+    if (c >= n_chunks) return;
+    const int lane = threadIdx.x & 63, i16 = lane & 15, k4 = lane >> 4;
+    const int p0 = ch_pptr[c], n = ch_pptr[c + 1] - p0;
+    bool pok[NP];
+    const C *x[NP];
+    C *dst[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int e = i16 + 16 * p;
+        pok[p] = e < n;
+        x[p] = in + (pok[p] ? pr_src[p0 + e] : 0);
+        dst[p] = part + (pok[p] ? pr_pos[p0 + e] : 0) * (int64_t)s;
+    }
+    const C *M = mat + ch_mat[c];
+    const int r = ch_rank[c];
+    if constexpr (KIND == 0) {
+        wv_dense<R>(M, s, cols, x[0], pok[0], dst[0], i16, k4);
+    } else if constexpr (KIND == 3 || KIND == 4) {
+        if (r < 0) {
+            if constexpr (KIND == 3)
+                wv_dense<R>(M, s, cols, x[0], pok[0], dst[0], i16, k4);
+            else
+                wv_dense_stream<R>(M, s, cols, x[0], pok[0], dst[0], i16, k4);
+        } else if (r <= 8)
+            wv_lowrank<R, 1, 1>(M, s, cols, r, x, pok, dst, i16, k4);
+        else if (r <= 16)
+            wv_lowrank<R, 2, 1>(M, s, cols, r, x, pok, dst, i16, k4);
+        else if (r <= 24)
+            wv_lowrank<R, 3, 1>(M, s, cols, r, x, pok, dst, i16, k4);
+        else
+            wv_lowrank<R, 4, 1>(M, s, cols, r, x, pok, dst, i16, k4);
+    } else {
+        if (r <= 8)
+            wv_lowrank<R, 1, NP>(M, s, cols, r, x, pok, dst, i16, k4);
+        else if (KIND == 1 || r <= 16)
+            wv_lowrank<R, 2, NP>(M, s, cols, r, x, pok, dst, i16, k4);
+        else if (r <= 24)
+            wv_lowrank<R, 3, NP>(M, s, cols, r, x, pok, dst, i16, k4);
+        else
+            wv_lowrank<R, 4, NP>(M, s, cols, r, x, pok, dst, i16, k4);
+    }
+}
+
+template <typename R, int TAG>
+static void launch_wave(const DChunks &c, dim3 grid, hipStream_t st, int n_seg, int n_out_prev, int s_prev,
+                        const int64_t *ro, const int64_t *rp, const typename Cx<R>::T *prev,
+                        typename Cx<R>::T *out_prev, const typename Cx<R>::T *mw, const typename Cx<R>::T *in,
+                        typename Cx<R>::T *part)
+{
+#define FDBEM_WAVE(K, NP)                                                                                            \
+    hipLaunchKernelGGL((k_wave_seg<R, TAG, K, NP>), grid, dim3(256), 0, st, n_seg, n_out_prev, s_prev, ro, rp,     \
+                       prev, out_prev, c.n, c.s, c.cols, c.ch_matw, c.ch_rank, c.ch_pptr, c.pr_src, c.pr_pos, mw, in, \
+                       part)
+    const bool two = c.pw == 32;
+    switch (c.wave_kind) {
+    case 0: FDBEM_WAVE(0, 1); break;
+    case 1: if (two) FDBEM_WAVE(1, 2); else FDBEM_WAVE(1, 1); break;
+    case 2: if (two) FDBEM_WAVE(2, 2); else FDBEM_WAVE(2, 1); break;
+    case 3: FDBEM_WAVE(3, 1); break;
+    default: FDBEM_WAVE(4, 1); break;
+    }
+#undef FDBEM_WAVE
+}
+
 __global__ void k_corr(const int64_t *__restrict__ rp, const int32_t *__restrict__ blk,
                        const double2 *__restrict__ val, const double2 *__restrict__ in, double2 *__restrict__ out,
                        int64_t n)
@@ -1194,6 +1547,78 @@ static DChunks upload_chunks(Device &D, const M2LChunks &C)
     return d;
 }
 
+// Row-major copies of a slab's operators for the wavefront chunk kernel,
+// shared by every slab that uses them (key: pool offset and transposed use).
+// Returns the per-chunk offsets into `pool`, or an empty vector when some
+// operator does not fit the kernel (a rank above 32); with pool == nullptr
+// every operator must already be there.
+static std::vector<int64_t> wave_offsets(const Plan &P, const M2LChunks &C,
+                                         std::unordered_map<int64_t, int64_t> &map, std::vector<double2> *pool)
+{
+    std::vector<int64_t> off(C.ch_mat.size());
+    for (size_t q = 0; q < C.ch_mat.size(); ++q) {
+        const int r = C.ch_rank[q];
+        if (r > WV_RMAX) return {};
+    }
+    const int s = C.s, cols = C.cols;
+    for (size_t q = 0; q < C.ch_mat.size(); ++q) {
+        const int r = C.ch_rank[q];
+        const int64_t key = 2 * C.ch_mat[q] + (C.trans ? 1 : 0);
+        auto it = map.find(key);
+        if (it != map.end()) {
+            off[q] = it->second;
+            continue;
+        }
+        if (!pool) throw std::runtime_error("translation operator missing from the wavefront pool");
+        const int64_t o = (int64_t)pool->size();
+        const cplx *M = P.matpool.data() + C.ch_mat[q];
+        auto put = [&](const cplx &v) { pool->push_back(make_double2(v.real(), v.imag())); };
+        if (r < 0) {
+            // A (s x cols): the pool holds A column-major, or its transpose for the transposed use
+            for (int i = 0; i < s; ++i)
+                for (int j = 0; j < cols; ++j) put(C.trans ? M[(int64_t)i * cols + j] : M[i + (int64_t)j * s]);
+        } else {
+            // U (s x r) at M and V (r x cols) at M + s r, both column-major in the pool
+            for (int i = 0; i < s; ++i)
+                for (int m = 0; m < r; ++m) put(M[i + (int64_t)m * s]);
+            for (int i = 0; i < r; ++i)
+                for (int j = 0; j < cols; ++j) put(M[(int64_t)s * r + i + (int64_t)j * r]);
+        }
+        map.emplace(key, o);
+        off[q] = o;
+    }
+    return off;
+}
+
+// Whether every operator of a translation list fits the wavefront kernel
+static bool wave_fits(const GemvList &G)
+{
+    for (int r : G.rank)
+        if (r > WV_RMAX) return false;
+    return true;
+}
+
+// Put a slab on the wavefront kernel when all its operators fit it: offsets
+// into the row-major pool (added to `pool`, or looked up once the pool is on
+// the device: pool == nullptr) and the kind of operators it holds.  Slabs of
+// 32 pairs per chunk take the wavefront kernel only when all are low-rank.
+static void attach_wave(Device &D, const Plan &P, const M2LChunks &C, DChunks &d, std::vector<double2> *pool)
+{
+    bool dense = false, low = false;
+    int rmax = 0;
+    for (int r : C.ch_rank) {
+        (r < 0 ? dense : low) = true;
+        rmax = std::max(rmax, r);
+    }
+    if (C.chunk > M2LC_CH && dense) return;
+    const std::vector<int64_t> off = wave_offsets(P, C, D.wmap, pool);
+    if (off.empty()) return;
+    d.ch_matw = dupload(D, off);
+    d.wave_kind = (dense && C.cols > 8 * WV_GMAX) ? 4 : !low ? 0 : dense ? 3 : rmax <= 16 ? 1 : 2;
+    d.matw = D.matw;
+    d.matwf = D.matwf;
+}
+
 static DLeaf upload_leaf(Device &D, const Plan &P, const std::vector<LeafTask> &T)
 {
     DLeaf L;
@@ -1231,7 +1656,7 @@ static void launch_slabs(const std::vector<DChunks> &S, void *part, const typena
 static void free_chunks(Device &D, DChunks &c)
 {
     for (void *p : {(void *)c.ch_mat, (void *)c.pr_tgt, (void *)c.pr_src, (void *)c.ch_rank, (void *)c.ch_pptr,
-                    (void *)c.pr_pos, (void *)c.red_out, (void *)c.red_ptr}) {
+                    (void *)c.pr_pos, (void *)c.red_out, (void *)c.red_ptr, (void *)c.ch_matw}) {
         if (!p) continue;
         auto it = std::find(D.allocs.begin(), D.allocs.end(), p);
         if (it != D.allocs.end()) D.allocs.erase(it);
@@ -1332,24 +1757,35 @@ static void autotune_m2l(Plan &P, Device &D)
         const std::vector<GemvList> &lists = kind == 0 ? P.m2l_lists : kind == 1 ? P.m2m_lists : P.l2l_lists;
         for (int l = 0; l < (int)slabs.size(); ++l) {
             if (slabs[l].empty()) continue;
+            // wavefront levels compare 16 and 32 pairs per wavefront (32 only when
+            // every slab stays on the wavefront kernel), the others 16 and 32 per workgroup
+            bool wave = false;
+            for (const DChunks &c : slabs[l]) wave = wave || c.ch_matw != nullptr;
             const GemvList &G = lists[l];
             std::vector<DChunks> alt;
-            for (const M2LChunks &C : build_chunk_slabs(G, 2 * M2LC_CH, slab_entries(G, P.opt.slab_mb)))
+            bool alt_ok = true;
+            for (const M2LChunks &C : build_chunk_slabs(G, 2 * M2LC_CH, slab_entries(G, P.opt.slab_mb))) {
                 alt.push_back(upload_chunks(D, C));
+                if (wave) {
+                    attach_wave(D, P, C, alt.back(), nullptr);
+                    alt_ok = alt_ok && alt.back().ch_matw != nullptr;
+                }
+            }
             size_t need = 0;
             for (const DChunks &c : alt) need = std::max(need, mfma_shm(c));
             double t16 = time(kind, slabs[l]), t32 = 1e30;
-            if (need <= (size_t)maxsh) {
-                set_mfma_lds(D, need);
+            if (wave ? alt_ok : need <= (size_t)maxsh) {
+                if (!wave) set_mfma_lds(D, need);
                 t32 = time(kind, alt);
             }
             const bool take = t32 < t16;
             if (take) std::swap(slabs[l], alt);
             for (DChunks &c : alt) free_chunks(D, c);
-            D.autotune.push_back({(double)l, (double)(take ? 2 * M2LC_CH : M2LC_CH), t16, t32, (double)kind});
+            D.autotune.push_back(
+                {(double)l, (double)(take ? 2 * M2LC_CH : M2LC_CH), t16, t32, (double)kind, wave ? 1.0 : 0.0});
             if (P.opt.verbose) {
-                std::fprintf(stderr, "[fdbem] autotune %s level %d: 16 pairs %.3f ms, 32 pairs %.3f ms\n", names[kind], l,
-                             t16, t32);
+                std::fprintf(stderr, "[fdbem] autotune %s level %d (%s): 16 pairs %.3f ms, 32 pairs %.3f ms\n",
+                             names[kind], l, wave ? "wavefront" : "workgroup", t16, t32);
                 std::fflush(stderr);
             }
         }
@@ -1481,12 +1917,16 @@ void device_upload(Plan &P)
             D.m2ms.resize(nlev);
             D.l2ls.resize(nlev);
             size_t part = 0, big = 0;
+            std::vector<double2> wpool;
             auto slabs = [&](const GemvList &G, std::vector<DChunks> &dst) {
                 if (G.out_off.empty()) return;
+                // the kernel is chosen per list, so that results do not depend on the slab size
+                const bool wave = P.opt.chunk_kernel == 0 && wave_fits(G);
                 for (const M2LChunks &C : build_chunk_slabs(G, M2LC_CH, slab_entries(G, P.opt.slab_mb))) {
                     dst.push_back(upload_chunks(D, C));
                     part = std::max(part, sizeof(double2) * (size_t)C.pr_pos.size() * (size_t)C.s);
                     big = std::max(big, dst.back().shm / 2);  // FP32 VALU kernel (FP64 runs on MFMA)
+                    if (wave) attach_wave(D, P, C, dst.back(), &wpool);
                 }
             };
             for (int l = 0; l < nlev; ++l) {
@@ -1498,10 +1938,28 @@ void device_upload(Plan &P)
                 D.tile_stats.push_back({(int64_t)D.m2ls[l].size(), nch, np, 0});
             }
             (void)big;
+            if (!wpool.empty()) {
+                // zero padding: masked operator loads read at most two entries past an operator's start
+                wpool.resize(wpool.size() + 16, make_double2(0, 0));
+                D.matw = dupload(D, wpool);
+                if (P.opt.precision >= 1) {
+                    std::vector<float2> wf(wpool.size());
+                    for (size_t i = 0; i < wf.size(); ++i) wf[i] = make_float2((float)wpool[i].x, (float)wpool[i].y);
+                    D.matwf = dupload(D, wf);
+                }
+                for (auto *v : {&D.m2ls, &D.m2ms, &D.l2ls})
+                    for (auto &lv : *v)
+                        for (DChunks &c : lv)
+                            if (c.ch_matw) {
+                                c.matw = D.matw;
+                                c.matwf = D.matwf;
+                            }
+            }
             size_t mf = 0;
             for (auto *v : {&D.m2ls, &D.m2ms, &D.l2ls})
                 for (const auto &lv : *v)
-                    for (const DChunks &c : lv) mf = std::max(mf, mfma_shm(c));
+                    for (const DChunks &c : lv)
+                        if (!c.ch_matw) mf = std::max(mf, mfma_shm(c));  // the wavefront kernel uses no LDS
             if (mf > (size_t)maxsh) throw std::runtime_error("translation operator too large for LDS");
             set_mfma_lds(D, mf);
             D.part_bytes = part;
@@ -1737,6 +2195,27 @@ static void launch_chunks(const DChunks &C, int cols, const typename Cx<R>::T *m
                        C.pr_src, mat, in, out, (const int64_t *)nullptr, (typename Cx<R>::T *)nullptr);
 }
 
+// row-major operator pool of a slab on the wavefront kernel (null: workgroup kernel)
+template <typename R>
+static const typename Cx<R>::T *wave_pool(const DChunks &c);
+template <>
+const double2 *wave_pool<double>(const DChunks &c)
+{
+    return c.ch_matw ? c.matw : nullptr;
+}
+template <>
+const float2 *wave_pool<float>(const DChunks &c)
+{
+    return c.ch_matw ? c.matwf : nullptr;
+}
+
+// workgroups of the wavefront kernel for n chunks: four chunks each, a multiple of the XCD count
+static int wave_grid(int n)
+{
+    const int nb = (n + 3) / 4;
+    return ((nb + kXcds - 1) / kXcds) * kXcds;
+}
+
 // partial-sum schedule: per slab, per-pair results into the scratch, then the per-output sums
 template <int TAG, bool TRANS, typename R>
 static void launch_slabs(const std::vector<DChunks> &S, void *part, const typename Cx<R>::T *mat,
@@ -1747,7 +2226,10 @@ static void launch_slabs(const std::vector<DChunks> &S, void *part, const typena
         if (!c.n) continue;
         const size_t shm = mfma_shm(c) * sizeof(R) / sizeof(double);
         const unsigned grid = (unsigned)(((c.n + kXcds - 1) / kXcds) * kXcds);
-        if (c.pw == 32)
+        if (const C *mw = wave_pool<R>(c))
+            launch_wave<R, TAG>(c, dim3(wave_grid(c.n)), st, 0, 0, 0, nullptr, nullptr, nullptr, nullptr, mw, in,
+                                (C *)part);
+        else if (c.pw == 32)
             hipLaunchKernelGGL((k_chunks_mfma<R, TRANS, 2, TAG>), dim3(grid), dim3(64 * M2LC_WAVES), shm, st, c.n, c.s,
                                c.cols, c.rmax, c.ch_mat, c.ch_rank, c.ch_pptr, c.pr_src, c.pr_pos, mat, in, (C *)part);
         else
@@ -1806,7 +2288,10 @@ static void launch_slabs_pipe(const std::vector<DChunks> &S, void *const part2[2
             n_seg = (int)((((n_out_prev + 3) / 4) + kXcds - 1) / kXcds * kXcds);
         }
         const dim3 grid((unsigned)(n_seg + chunk_grid)), block(64 * M2LC_WAVES);
-        if (c.pw == 32)
+        if (const C *mw = wave_pool<R>(c))
+            launch_wave<R, TAG>(c, dim3((unsigned)(n_seg + wave_grid(c.n))), st, n_seg, n_out_prev, s_prev, ro, rp,
+                                prev, out_prev, mw, in, (C *)part);
+        else if (c.pw == 32)
             hipLaunchKernelGGL((k_chunks_seg<R, TRANS, 2, TAG>), grid, block, shm, st, n_seg, n_out_prev, s_prev, ro, rp,
                                prev, out_prev, c.n, c.s, c.cols, c.rmax, c.ch_mat, c.ch_rank, c.ch_pptr, c.pr_src,
                                c.pr_pos, mat, in, (C *)part);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <unordered_map>
 
 #include "plan.hpp"
 
@@ -36,6 +37,12 @@ struct DChunks {
     int n_out = 0, pw = 16;          // pw: pairs per chunk (16 or 32)
     int64_t n_entries = 0;
     int64_t *pr_pos = nullptr, *red_out = nullptr, *red_ptr = nullptr;
+    // wavefront kernel: operator offsets in the row-major pool (null: the workgroup kernel runs)
+    int64_t *ch_matw = nullptr;
+    int wave_kind = 0;               // operators of the slab: 0 dense, 1 rank <= 16, 2 low-rank, 3 both,
+                                     // 4 both with dense operators of more than 64 columns
+    const double2 *matw = nullptr;
+    const float2 *matwf = nullptr;
 };
 
 struct DCorr {
@@ -95,6 +102,9 @@ struct Device {
     double2 *t_Wt = nullptr;     // the same, each transposed (element (r, a) at a + r |Y|)
     // translations
     double2 *mat = nullptr;
+    double2 *matw = nullptr;           // row-major operators of the wavefront chunk kernel
+    float2 *matwf = nullptr;
+    std::unordered_map<int64_t, int64_t> wmap;  // pool offset * 2 + transposed use -> offset in matw
     std::vector<DGemv> m2m, m2l, l2l;  // per level
     std::vector<DTiles> m2lt;          // per level, tiled M2L
     std::vector<DChunks> m2lc;         // per level, operator-chunk M2L
@@ -133,8 +143,9 @@ struct Device {
         void *out = nullptr;
     };
     int use_graph = 0;
-    // per tuned (translation, level): level, pairs per chunk, ms(16), ms(32), kind (0 M2L, 1 M2M, 2 L2L)
-    std::vector<std::array<double, 5>> autotune;
+    // per tuned (translation, level): level, pairs per chunk, ms(16), ms(32), kind (0 M2L, 1 M2M, 2 L2L),
+    // kernel (0 workgroup chunks, 1 wavefront chunks: not tuned)
+    std::vector<std::array<double, 6>> autotune;
     size_t mfma_lds = 65536;   // dynamic LDS limit set on the chunk kernels
     hipStream_t cap = nullptr;
     std::vector<GraphEntry> graphs;

@@ -37,6 +37,7 @@ struct Options {
     int autotune = 1;        // time the M2L/M2M/L2L chunk shapes on the plan and keep the faster
     int slab_mb = 1024;      // scratch of per-pair translation results per slab (MiB)
     int serial_slabs = 0;    // 0: two slab buffers, each launch also sums the previous slab; 1: one buffer
+    int chunk_kernel = 0;    // 0: wavefront chunk kernel where an operator fits it; 1: workgroup kernel only
     // k of the coupling: alpha = i / alpha_k()
     double alpha_k(double k) const { return k / coupling; }
 };

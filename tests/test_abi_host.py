@@ -48,6 +48,17 @@ def test_build_rejects_bad_arguments(k, eps):
     assert e.value.code == _abi.FDA_EINVAL
 
 
+@pytest.mark.parametrize("opt", [{"chunk_kernel": 2}, {"chunk_kernel": -1}, {"original": 2}, {"hf_template": 5}])
+def test_options_out_of_range_are_refused(opt):
+    pts, nrm, w = _geom(10)
+    with pytest.raises(_abi.FdaError) as e:
+        fdb.build(pts, nrm, w, 5.0, 1e-4, **opt)
+    assert e.value.code == _abi.FDA_EINVAL
+    with pytest.raises(_abi.FdaError) as e:
+        fdb.analyze(pts, nrm, w, 5.0, 1e-4, **opt)
+    assert e.value.code == _abi.FDA_EINVAL
+
+
 def test_build_rejects_empty_and_mismatched_elements():
     with pytest.raises(_abi.FdaError) as e:
         fdb.build(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), 5.0, 1e-4)

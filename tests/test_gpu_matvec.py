@@ -92,31 +92,38 @@ def test_fda_high_frequency_sampled_rows(torch):
 
 
 def test_m2l_kernels_agree_and_tiles_are_deterministic(torch):
-    """The four translation schedules (operator chunks with per-pair results
-    summed per output, operator chunks with atomic adds, per-target GEMV,
-    workgroup target tiles) apply the same operators; the partial-sum and
-    tiled ones are bitwise reproducible."""
+    """The translation schedules (operator chunks with per-pair results
+    summed per output, on the wavefront or on the workgroup chunk kernel;
+    operator chunks with atomic adds; per-target GEMV; workgroup target
+    tiles) apply the same operators; the partial-sum and tiled ones are
+    bitwise reproducible."""
     import paper_1311_5202_amd as fdb
 
     _, pts, nrm, w = _geom(12)
     k = 16.0
     u = torch.from_numpy(synth.random_densities(len(w), 3)).cuda()
     outs = {}
-    modes = {"partial": 3, "chunks": 0, "gemv": 1, "tiles": 2}
-    for name, tile in (("partial", 0), ("chunks", 1), ("gemv", -1), ("tiles", 16)):
+    modes = {"partial": 3, "partial_wg": 3, "chunks": 0, "gemv": 1, "tiles": 2}
+    for name, tile, ck in (("partial", 0, 0), ("partial_wg", 0, 1), ("chunks", 1, 0), ("gemv", -1, 0),
+                           ("tiles", 16, 0)):
         print(f"[m2l] schedule {name}", flush=True)
-        plan = fdb.build(pts, nrm, w, k, 1e-4, m2l_tile=tile)
-        assert plan.stats()["m2l_mode"] == modes[name]
+        plan = fdb.build(pts, nrm, w, k, 1e-4, m2l_tile=tile, chunk_kernel=ck)
+        st = plan.stats()
+        assert st["m2l_mode"] == modes[name]
+        if name.startswith("partial"):
+            kernels = {t["kernel"] for key in ("m2l_autotune", "m2m_autotune", "l2l_autotune") for t in st[key]}
+            print(f"[m2l] {name}: chunk kernels {sorted(kernels)}", flush=True)
+            assert ("wavefront" in kernels) == (ck == 0)
         a = plan.matvec(u, "RAW_H").cpu().numpy()
         b = plan.matvec(u, "RAW_H").cpu().numpy()
-        if name in ("partial", "tiles"):
+        if name in ("partial", "partial_wg", "tiles"):
             assert np.array_equal(a, b)
         else:
             assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
         outs[name] = a
         plan.close()
     ref = outs["gemv"]
-    for name in ("partial", "chunks", "tiles"):
+    for name in ("partial", "partial_wg", "chunks", "tiles"):
         assert np.max(np.abs(outs[name] - ref)) <= 1e-12 * np.max(np.abs(ref)), name
 
 
@@ -187,21 +194,22 @@ def test_table1_accuracy_against_paper(torch, n_oct, k_over_pi, eps, original):
     plan.close()
 
 
-def test_autotuned_chunk_shapes_give_identical_results(torch):
+@pytest.mark.parametrize("chunk_kernel", [0, 1])
+def test_autotuned_chunk_shapes_give_identical_results(torch, chunk_kernel):
     """The builder's autotuner picks 16 or 32 pairs per chunk per level for
-    M2L, M2M and L2L; either shape gives bitwise the same mat-vec, and the
-    choices are reported."""
+    M2L, M2M and L2L (per wavefront or per workgroup); either shape gives
+    bitwise the same mat-vec, and the choices are reported."""
     import paper_1311_5202_amd as fdb
 
     _, pts, nrm, w = _geom(16)
     k = 24.0
     u = torch.from_numpy(synth.random_densities(len(w), 5)).cuda()
-    ref_plan = fdb.build(pts, nrm, w, k, 1e-4, autotune=0)
+    ref_plan = fdb.build(pts, nrm, w, k, 1e-4, autotune=0, chunk_kernel=chunk_kernel)
     ref = ref_plan.matvec(u, "RAW_H")
     st0 = ref_plan.stats()
     assert st0["m2l_autotune"] == [] and st0["m2m_autotune"] == [] and st0["l2l_autotune"] == []
     ref_plan.close()
-    plan = fdb.build(pts, nrm, w, k, 1e-4, autotune=1)
+    plan = fdb.build(pts, nrm, w, k, 1e-4, autotune=1, chunk_kernel=chunk_kernel)
     st = plan.stats()
     for key in ("m2l_autotune", "m2m_autotune", "l2l_autotune"):
         tuned = st[key]
