@@ -1160,43 +1160,57 @@ __device__ __forceinline__ void wv_dense(const typename Cx<R>::T *__restrict__ A
     }
 }
 
-// Y = A X for a dense operator of any width: the source groups are read
-// again for every pair of row tiles (same products in the same order as
-// wv_dense, so the same result bit for bit)
-template <typename R>
+// Y = A X for a dense operator of any width on NP tiles of 16 pairs: the
+// source groups are read again for every pair of row tiles (same products
+// in the same order as wv_dense, so the same result bit for bit)
+template <typename R, int NP>
 __device__ __forceinline__ void wv_dense_stream(const typename Cx<R>::T *__restrict__ A, int s, int cols,
-                                                const typename Cx<R>::T *__restrict__ x, bool pok,
-                                                typename Cx<R>::T *dst, int i16, int k4)
+                                                const typename Cx<R>::T *const x[NP], const bool pok[NP],
+                                                typename Cx<R>::T *const dst[NP], int i16, int k4)
 {
     typedef typename Mf<R>::V V;
     const int G = (2 * cols + 15) >> 4, n_rt = (2 * s + 15) >> 4, rw = Mf<R>::rho(i16);
     int rt = 0;
     for (; rt + 1 < n_rt; rt += 2) {
-        V y0 = {0, 0, 0, 0}, y1 = y0;
+        V y0[NP], y1[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) y0[p] = y1[p] = V{0, 0, 0, 0};
         for (int g = 0; g < G; ++g) {
-            R a0[4], a1[4], xb[4];
-            wv_b<R>(x, cols, 8 * g + 2 * k4, pok, xb);
+            R a0[4], a1[4], xb[NP][4];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) wv_b<R>(x[p], cols, 8 * g + 2 * k4, pok[p], xb[p]);
             wv_a<R>(A, s, cols, 16 * rt + rw, 8 * g + 2 * k4, a0);
             wv_a<R>(A, s, cols, 16 * rt + 16 + rw, 8 * g + 2 * k4, a1);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                y0 = Mf<R>::mma(a0[t], xb[t], y0);
-                y1 = Mf<R>::mma(a1[t], xb[t], y1);
-            }
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    y0[p] = Mf<R>::mma(a0[t], xb[p][t], y0[p]);
+                    y1[p] = Mf<R>::mma(a1[t], xb[p][t], y1[p]);
+                }
         }
-        wv_store<R>(dst, pok, s, rt, k4, y0);
-        wv_store<R>(dst, pok, s, rt + 1, k4, y1);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            wv_store<R>(dst[p], pok[p], s, rt, k4, y0[p]);
+            wv_store<R>(dst[p], pok[p], s, rt + 1, k4, y1[p]);
+        }
     }
     if (rt < n_rt) {
-        V y0 = {0, 0, 0, 0};
+        V y0[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) y0[p] = V{0, 0, 0, 0};
         for (int g = 0; g < G; ++g) {
-            R a0[4], xb[4];
-            wv_b<R>(x, cols, 8 * g + 2 * k4, pok, xb);
+            R a0[4], xb[NP][4];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) wv_b<R>(x[p], cols, 8 * g + 2 * k4, pok[p], xb[p]);
             wv_a<R>(A, s, cols, 16 * rt + rw, 8 * g + 2 * k4, a0);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) y0 = Mf<R>::mma(a0[t], xb[t], y0);
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) y0[p] = Mf<R>::mma(a0[t], xb[p][t], y0[p]);
         }
-        wv_store<R>(dst, pok, s, rt, k4, y0);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) wv_store<R>(dst[p], pok[p], s, rt, k4, y0[p]);
     }
 }
 
@@ -1317,8 +1331,9 @@ __device__ __forceinline__ void wv_lowrank(const typename Cx<R>::T *__restrict__
 // Chunk workgroups are dealt to the XCDs in contiguous ranges.  KIND names
 // the operators a slab holds, so that an instance keeps only the registers
 // its paths need: 0 dense, 1 low-rank of rank <= 16, 2 low-rank, 3 both, 4
-// both with dense operators of more than 64 columns.
-// NP: tiles of 16 pairs per chunk (2 only for low-rank slabs).
+// both with the dense sources read per row-tile pair (any width), 5 dense
+// read so.
+// NP: tiles of 16 pairs per chunk (2 not with kinds 0 and 3).
 template <typename R, int TAG, int KIND, int NP>
 __global__ __launch_bounds__(256) void k_wave_seg(
     int n_seg, int n_out_prev, int s_prev, const int64_t *__restrict__ red_out_prev,
@@ -1329,7 +1344,7 @@ __global__ __launch_bounds__(256) void k_wave_seg(
     const typename Cx<R>::T *__restrict__ in, typename Cx<R>::T *__restrict__ part)
 {
     using C = typename Cx<R>::T;
-    static_assert(NP == 1 || (KIND == 1 || KIND == 2), "two pair tiles only for low-rank slabs");
+    static_assert(NP == 1 || (KIND != 0 && KIND != 3), "two pair tiles need the streaming dense path");
     if ((int)blockIdx.x < n_seg) {
         seg_sum_block<R>(blockIdx.x, n_out_prev, s_prev, red_out_prev, red_ptr_prev, prev, out_prev);
         return;
@@ -1353,13 +1368,12 @@ __global__ __launch_bounds__(256) void k_wave_seg(
     const int r = ch_rank[c];
     if constexpr (KIND == 0) {
         wv_dense<R>(M, s, cols, x[0], pok[0], dst[0], i16, k4);
-    } else if constexpr (KIND == 3 || KIND == 4) {
-        if (r < 0) {
-            if constexpr (KIND == 3)
-                wv_dense<R>(M, s, cols, x[0], pok[0], dst[0], i16, k4);
-            else
-                wv_dense_stream<R>(M, s, cols, x[0], pok[0], dst[0], i16, k4);
-        } else if (r <= 8)
+    } else if constexpr (KIND == 5) {
+        wv_dense_stream<R, NP>(M, s, cols, x, pok, dst, i16, k4);
+    } else if constexpr (KIND == 3) {
+        if (r < 0)
+            wv_dense<R>(M, s, cols, x[0], pok[0], dst[0], i16, k4);
+        else if (r <= 8)
             wv_lowrank<R, 1, 1>(M, s, cols, r, x, pok, dst, i16, k4);
         else if (r <= 16)
             wv_lowrank<R, 2, 1>(M, s, cols, r, x, pok, dst, i16, k4);
@@ -1367,6 +1381,17 @@ __global__ __launch_bounds__(256) void k_wave_seg(
             wv_lowrank<R, 3, 1>(M, s, cols, r, x, pok, dst, i16, k4);
         else
             wv_lowrank<R, 4, 1>(M, s, cols, r, x, pok, dst, i16, k4);
+    } else if constexpr (KIND == 4) {
+        if (r < 0)
+            wv_dense_stream<R, NP>(M, s, cols, x, pok, dst, i16, k4);
+        else if (r <= 8)
+            wv_lowrank<R, 1, NP>(M, s, cols, r, x, pok, dst, i16, k4);
+        else if (r <= 16)
+            wv_lowrank<R, 2, NP>(M, s, cols, r, x, pok, dst, i16, k4);
+        else if (r <= 24)
+            wv_lowrank<R, 3, NP>(M, s, cols, r, x, pok, dst, i16, k4);
+        else
+            wv_lowrank<R, 4, NP>(M, s, cols, r, x, pok, dst, i16, k4);
     } else {
         if (r <= 8)
             wv_lowrank<R, 1, NP>(M, s, cols, r, x, pok, dst, i16, k4);
@@ -1395,7 +1420,8 @@ static void launch_wave(const DChunks &c, dim3 grid, hipStream_t st, int n_seg, 
     case 1: if (two) FDBEM_WAVE(1, 2); else FDBEM_WAVE(1, 1); break;
     case 2: if (two) FDBEM_WAVE(2, 2); else FDBEM_WAVE(2, 1); break;
     case 3: FDBEM_WAVE(3, 1); break;
-    default: FDBEM_WAVE(4, 1); break;
+    case 4: if (two) FDBEM_WAVE(4, 2); else FDBEM_WAVE(4, 1); break;
+    default: if (two) FDBEM_WAVE(5, 2); else FDBEM_WAVE(5, 1); break;
     }
 #undef FDBEM_WAVE
 }
@@ -1600,8 +1626,7 @@ static bool wave_fits(const GemvList &G)
 
 // Put a slab on the wavefront kernel when all its operators fit it: offsets
 // into the row-major pool (added to `pool`, or looked up once the pool is on
-// the device: pool == nullptr) and the kind of operators it holds.  Slabs of
-// 32 pairs per chunk take the wavefront kernel only when all are low-rank.
+// the device: pool == nullptr) and the kind of operators it holds.
 static void attach_wave(Device &D, const Plan &P, const M2LChunks &C, DChunks &d, std::vector<double2> *pool)
 {
     bool dense = false, low = false;
@@ -1610,11 +1635,12 @@ static void attach_wave(Device &D, const Plan &P, const M2LChunks &C, DChunks &d
         (r < 0 ? dense : low) = true;
         rmax = std::max(rmax, r);
     }
-    if (C.chunk > M2LC_CH && dense) return;
     const std::vector<int64_t> off = wave_offsets(P, C, D.wmap, pool);
     if (off.empty()) return;
     d.ch_matw = dupload(D, off);
-    d.wave_kind = (dense && C.cols > 8 * WV_GMAX) ? 4 : !low ? 0 : dense ? 3 : rmax <= 16 ? 1 : 2;
+    // dense operators on 32-pair chunks, or wider than 64 columns, take the streaming dense path
+    const bool stream = C.cols > 8 * WV_GMAX || C.chunk > M2LC_CH;
+    d.wave_kind = !low ? (stream ? 5 : 0) : !dense ? (rmax <= 16 ? 1 : 2) : stream ? 4 : 3;
     d.matw = D.matw;
     d.matwf = D.matwf;
 }

@@ -40,7 +40,7 @@ struct DChunks {
     // wavefront kernel: operator offsets in the row-major pool (null: the workgroup kernel runs)
     int64_t *ch_matw = nullptr;
     int wave_kind = 0;               // operators of the slab: 0 dense, 1 rank <= 16, 2 low-rank, 3 both,
-                                     // 4 both with dense operators of more than 64 columns
+                                     // 4 both and 5 dense with the sources read per row-tile pair
     const double2 *matw = nullptr;
     const float2 *matwf = nullptr;
 };
