@@ -178,11 +178,19 @@ __global__ void k_fill_zero(C *p, int64_t n)
     if (i < n) p[i].x = 0, p[i].y = 0;
 }
 
+// weighted densities to tree order, also into the last 16 bytes of each
+// point's 64-byte near-field record (pn: 8 doubles per point), so that the
+// near-field kernel reads a source with one 64-byte record
 __global__ void k_permute_in(const double2 *__restrict__ in, const int64_t *__restrict__ perm,
-                             const double *__restrict__ w, double2 *__restrict__ dens, int64_t n)
+                             const double *__restrict__ w, double2 *__restrict__ dens, double *__restrict__ pn,
+                             int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dens[i] = cscale(in[perm[i]], w[i]);
+    if (i < n) {
+        const double2 d = cscale(in[perm[i]], w[i]);
+        dens[i] = d;
+        *(double2 *)(pn + 8 * i + 6) = d;
+    }
 }
 
 __global__ void k_permute_out(const double2 *__restrict__ res, const int64_t *__restrict__ perm,
@@ -196,15 +204,17 @@ __global__ void k_permute_out(const double2 *__restrict__ res, const int64_t *__
     out[j] = v;
 }
 
-// Near field.  One 64-lane workgroup per target leaf, leaves launched in
-// decreasing order of work: lane = t + nt q for
-// target t of the nt targets and source slice q of S = 64 / nt, so small
-// leaves still fill the wavefront; each lane takes two sources per step, and
+// Near field.  One 64-lane workgroup per target leaf; the leaf's near-list
+// source ranges are concatenated (their point indices staged in LDS) and its
+// targets run in blocks of nt (chosen on the host to fill the lanes): lane =
+// t + nt q for target t of the block and source slice q of S = 64 / nt, so
+// small blocks still fill the wavefront and no slice idles at the end of a
+// short range; each lane takes two sources per step, and
 // the slices are added in order q = 0, 1, .. with cross-lane shuffles.  The
 // kernel shape is a template parameter so every operator evaluates only its
 // nonzero terms.
 struct PN {
-    double x, y, z, nx, ny, nz, pad0, pad1;
+    double x, y, z, nx, ny, nz, dre, dim;  // position, normal, weighted density of the current mat-vec
 };
 
 enum { OPK_H = 0, OPK_G = 1, OPK_T1 = 2 };
@@ -244,50 +254,70 @@ __device__ __forceinline__ typename Cx<R>::T kernel_op(R dx, R dy, R dz, R nxx, 
     return cmul(G, t);
 }
 
+constexpr int P2P_LIST = 2048;  // source indices of a leaf's near list held in LDS per pass
+
 template <int OPK, typename R>
-__global__ __launch_bounds__(64) void k_p2p(int n_leaf, const int64_t *__restrict__ ts, const int64_t *__restrict__ te,
-                                             const int *__restrict__ ptr, const int64_t *__restrict__ ss,
-                                             const int64_t *__restrict__ se, const PN *__restrict__ pn,
-                                             const double2 *__restrict__ dens, double2 *__restrict__ res, double k,
+__global__ __launch_bounds__(64) void k_p2p(int n_leaf, const int64_t *__restrict__ ts, const int *__restrict__ bptr,
+                                             const int *__restrict__ bsz, const int *__restrict__ ptr,
+                                             const int64_t *__restrict__ ss, const int64_t *__restrict__ se,
+                                             const PN *__restrict__ pn, double2 *__restrict__ res, double k,
                                              double alpha_im)
 {
     using C = typename Cx<R>::T;
+    __shared__ int list[P2P_LIST];
     const int leaf = blockIdx.x;
     if (leaf >= n_leaf) return;
     const int lane = threadIdx.x;
     const R kr = (R)k, ik = (R)alpha_im;
-    const int64_t t0 = ts[leaf], t1 = te[leaf];
     const int e0 = ptr[leaf], e1 = ptr[leaf + 1];
-    for (int64_t ib = t0; ib < t1; ib += 64) {
-        // lane = t + nt q: target t, source slice q of S = 64 / nt
-        const int nt = (int)min((int64_t)64, t1 - ib);
+    // the near list's source ranges, concatenated: virtual source v in [0, tot)
+    int tot = 0;
+    for (int e = e0; e < e1; ++e) tot += (int)(se[e] - ss[e]);
+    int64_t ib = ts[leaf];
+    for (int blk = bptr[leaf]; blk < bptr[leaf + 1]; ib += bsz[blk], ++blk) {
+        // lane = t + nt q: target t of the block's nt (<= 64), source slice q of S = 64 / nt
+        const int nt = bsz[blk];
         const int S = 64 / nt;
         const int q = lane / nt, t = lane - q * nt;
         const bool act = q < S;
         const int64_t i = ib + t;
         const PN X = pn[i];
+        // the difference in FP64 keeps the phase accurate; the kernel runs in R.
+        // The self pair (r = 0) is excluded by a select, not a branch.
+        auto term = [&](const PN &Y, int64_t j) {
+            C K = kernel_op<OPK, R>((R)(X.x - Y.x), (R)(X.y - Y.y), (R)(X.z - Y.z), (R)X.nx, (R)X.ny, (R)X.nz,
+                                    (R)Y.nx, (R)Y.ny, (R)Y.nz, kr, ik);
+            return j == i ? Cx<R>::mk(0, 0) : K;
+        };
         C acc = Cx<R>::mk(0, 0);
-        if (act) {
-            for (int e = e0; e < e1; ++e) {
-                const int64_t s1 = se[e];
-                // the difference in FP64 keeps the phase accurate; the kernel runs in R.
-                // The self pair (r = 0) is excluded by a select, not a branch.
-                auto term = [&](const PN &Y, int64_t j) {
-                    C K = kernel_op<OPK, R>((R)(X.x - Y.x), (R)(X.y - Y.y), (R)(X.z - Y.z), (R)X.nx, (R)X.ny,
-                                            (R)X.nz, (R)Y.nx, (R)Y.ny, (R)Y.nz, kr, ik);
-                    return j == i ? Cx<R>::mk(0, 0) : K;
-                };
-                int64_t j = ss[e] + q;
-                // two sources per step, both loaded before either kernel is evaluated;
-                // terms are added in source order
-                for (; j + S < s1; j += 2 * S) {
-                    const PN Y0 = pn[j], Y1 = pn[j + S];
-                    const C d0 = from64<C>(dens[j]), d1 = from64<C>(dens[j + S]);
-                    const C K0 = term(Y0, j), K1 = term(Y1, j + S);
+        for (int v0 = 0; v0 < tot; v0 += P2P_LIST) {
+            const int nv = min(P2P_LIST, tot - v0);
+            __syncthreads();  // the previous pass has read its indices
+            for (int e = e0, cum = 0; e < e1 && cum < v0 + nv; ++e) {
+                const int64_t a = ss[e];
+                const int len = (int)(se[e] - a);
+                const int lo = max(v0 - cum, 0), hi = min(v0 + nv - cum, len);
+                for (int l = lo + lane; l < hi; l += 64) list[cum + l - v0] = (int)(a + l);
+                cum += len;
+            }
+            __syncthreads();
+            if (act) {
+                // slice q takes virtual sources q, q + S, .. of the pass, two per step,
+                // both loaded before either kernel is evaluated, added in that order
+                int v = q;
+                for (; v + S < nv; v += 2 * S) {
+                    const int j0 = list[v], j1 = list[v + S];
+                    const PN Y0 = pn[j0], Y1 = pn[j1];
+                    const C d0 = from64<C>(make_double2(Y0.dre, Y0.dim)), d1 = from64<C>(make_double2(Y1.dre, Y1.dim));
+                    const C K0 = term(Y0, j0), K1 = term(Y1, j1);
                     acc = cadd(acc, cmul(K0, d0));
                     acc = cadd(acc, cmul(K1, d1));
                 }
-                if (j < s1) acc = cadd(acc, cmul(term(pn[j], j), from64<C>(dens[j])));
+                if (v < nv) {
+                    const int j0 = list[v];
+                    const PN Y0 = pn[j0];
+                    acc = cadd(acc, cmul(term(Y0, j0), from64<C>(make_double2(Y0.dre, Y0.dim))));
+                }
             }
         }
         // slices added in order q = 0, 1, .., S - 1 into the lanes of slice 0
@@ -1842,20 +1872,44 @@ void device_upload(Plan &P)
         D.pn = (void *)dupload(D, pnh);
     }
     D.n_leaf = (int)P.leaves.size();
+    if (P.N >= (int64_t)INT32_MAX) throw std::runtime_error("more points than the near-field kernel indexes (2^31 - 1)");
     {
-        // target leaves: the heaviest 2% by P2P work first, in decreasing order
-        // (one wavefront each: per block of 64 targets, the source steps of
-        // 64/nt slices), so the longest wavefronts do not end up in the tail;
-        // the rest in tree order, where neighbouring leaves share sources in L2
+        // target blocks: a leaf's targets are cut into blocks of nt targets,
+        // each run with 64 / nt slices of the leaf's concatenated sources, and
+        // the cut minimises the leaf's source steps (sum over blocks of
+        // ceil(n_sources / slices), plus two steps per block); blocks of 64,
+        // 32, 21, 16, .. fill 64, 64, 63, 64, .. lanes where a whole leaf of,
+        // say, 22 targets would leave 20 lanes idle.  Target leaves: the heaviest 2%
+        // by that work first, in decreasing order (one wavefront each), so the
+        // longest wavefronts do not end up in the tail; the rest in tree
+        // order, where neighbouring leaves share sources in L2
         const int nl = (int)P.p2p_tgt_start.size();
+        static const int kBlock[] = {64, 32, 21, 16, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2, 1};
+        constexpr int nB = (int)(sizeof(kBlock) / sizeof(kBlock[0]));
         std::vector<double> work(nl, 0.0);
+        std::vector<std::vector<int>> blocks(nl);
+#pragma omp parallel for schedule(dynamic, 256)
         for (int t = 0; t < nl; ++t) {
-            const int64_t nt_all = P.p2p_tgt_end[t] - P.p2p_tgt_start[t];
-            for (int64_t ib = 0; ib < nt_all; ib += 64) {
-                const int64_t nt = std::min<int64_t>(64, nt_all - ib), S = 64 / nt;
-                for (int e = P.p2p_ptr[t]; e < P.p2p_ptr[t + 1]; ++e)
-                    work[t] += (double)((P.p2p_src_end[e] - P.p2p_src_start[e] + S - 1) / S);
+            const int nt_all = (int)(P.p2p_tgt_end[t] - P.p2p_tgt_start[t]);
+            int64_t tot = 0;
+            for (int e = P.p2p_ptr[t]; e < P.p2p_ptr[t + 1]; ++e) tot += P.p2p_src_end[e] - P.p2p_src_start[e];
+            double cost[nB];
+            for (int b = 0; b < nB; ++b) {
+                const int64_t S = 64 / kBlock[b];
+                cost[b] = 2.0 + (double)((tot + S - 1) / S);  // source steps, plus staging and the slice sum
             }
+            std::vector<double> best(nt_all + 1, 0.0);
+            std::vector<int> pick(nt_all + 1, 0);
+            for (int n = 1; n <= nt_all; ++n) {
+                best[n] = 1e300;
+                for (int b = 0; b < nB; ++b)
+                    if (kBlock[b] <= n && cost[b] + best[n - kBlock[b]] < best[n]) {
+                        best[n] = cost[b] + best[n - kBlock[b]];
+                        pick[n] = kBlock[b];
+                    }
+            }
+            work[t] = best[nt_all];
+            for (int n = nt_all; n > 0; n -= pick[n]) blocks[t].push_back(pick[n]);
         }
         std::vector<int> order(nl);
         for (int t = 0; t < nl; ++t) order[t] = t;
@@ -1868,22 +1922,24 @@ void device_upload(Plan &P)
             for (int t = 0; t < nl; ++t)
                 if (!first[t]) order[q++] = t;
         }
-        std::vector<int64_t> ts(nl), te(nl), ss, se;
-        std::vector<int> ptr(nl + 1, 0);
+        std::vector<int64_t> ts(nl), ss, se;
+        std::vector<int> ptr(nl + 1, 0), bptr(nl + 1, 0), bsz;
         ss.reserve(P.p2p_src_start.size());
         se.reserve(P.p2p_src_end.size());
         for (int q = 0; q < nl; ++q) {
             const int t = order[q];
             ts[q] = P.p2p_tgt_start[t];
-            te[q] = P.p2p_tgt_end[t];
             for (int e = P.p2p_ptr[t]; e < P.p2p_ptr[t + 1]; ++e) {
                 ss.push_back(P.p2p_src_start[e]);
                 se.push_back(P.p2p_src_end[e]);
             }
             ptr[q + 1] = (int)ss.size();
+            bsz.insert(bsz.end(), blocks[t].begin(), blocks[t].end());
+            bptr[q + 1] = (int)bsz.size();
         }
         D.p2p_ts = dupload(D, ts);
-        D.p2p_te = dupload(D, te);
+        D.p2p_bptr = dupload(D, bptr);
+        D.p2p_bsz = dupload(D, bsz);
         D.p2p_ptr = dupload(D, ptr);
         D.p2p_ss = dupload(D, ss);
         D.p2p_se = dupload(D, se);
@@ -2200,14 +2256,14 @@ static void launch_p2p(Plan &P, Device &D, int op, hipStream_t st)
     const dim3 g(D.n_leaf), b(64);
     const double ai = 1.0 / P.opt.alpha_k(P.k);
     if (opk == OPK_H)
-        hipLaunchKernelGGL((k_p2p<OPK_H, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
-                           (const PN *)D.pn, D.dens, D.res, P.k, ai);
+        hipLaunchKernelGGL((k_p2p<OPK_H, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_bptr, D.p2p_bsz, D.p2p_ptr, D.p2p_ss, D.p2p_se,
+                           (const PN *)D.pn, D.res, P.k, ai);
     else if (opk == OPK_G)
-        hipLaunchKernelGGL((k_p2p<OPK_G, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
-                           (const PN *)D.pn, D.dens, D.res, P.k, ai);
+        hipLaunchKernelGGL((k_p2p<OPK_G, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_bptr, D.p2p_bsz, D.p2p_ptr, D.p2p_ss, D.p2p_se,
+                           (const PN *)D.pn, D.res, P.k, ai);
     else
-        hipLaunchKernelGGL((k_p2p<OPK_T1, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss,
-                           D.p2p_se, (const PN *)D.pn, D.dens, D.res, P.k, ai);
+        hipLaunchKernelGGL((k_p2p<OPK_T1, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_bptr, D.p2p_bsz, D.p2p_ptr, D.p2p_ss,
+                           D.p2p_se, (const PN *)D.pn, D.res, P.k, ai);
 }
 
 template <int TAG, bool TRANS, typename R>
@@ -2427,7 +2483,7 @@ void device_matvec(Plan &P, int op, const double2 *in, double2 *out, hipStream_t
     const bool tm = D.timing != 0;
     hipEvent_t *ev = tm ? &D.ev[(size_t)(D.ring_pos % Device::kRing) * 10] : nullptr;
     if (tm) HIP_CHECK(hipEventRecord(ev[0], st));
-    hipLaunchKernelGGL(k_permute_in, dim3(nblk(N, 256)), dim3(256), 0, st, in, D.perm, D.w, D.dens, N);
+    hipLaunchKernelGGL(k_permute_in, dim3(nblk(N, 256)), dim3(256), 0, st, in, D.perm, D.w, D.dens, (double *)D.pn, N);
     if (tm) HIP_CHECK(hipEventRecord(ev[1], st));
     if (f32)
         launch_p2p<float, OpCf>(P, D, op, st);
