@@ -205,11 +205,12 @@ __global__ void k_permute_out(const double2 *__restrict__ res, const int64_t *__
 }
 
 // Near field.  One 64-lane workgroup per target leaf; the leaf's near-list
-// source ranges are concatenated (their point indices staged in LDS) and its
-// targets run in blocks of nt (chosen on the host to fill the lanes): lane =
-// t + nt q for target t of the block and source slice q of S = 64 / nt, so
-// small blocks still fill the wavefront and no slice idles at the end of a
-// short range; each lane takes two sources per step, and
+// source ranges are concatenated (their point indices staged in LDS), so no
+// slice idles at the end of a short range, and its targets run in blocks of
+// up to 64: lane = t + nt q for target t of the nt and source slice q of S =
+// 64 / nt, so small leaves still fill the wavefront (cutting a leaf into
+// smaller blocks that fill more lanes was slower: more distinct sources per
+// load instruction); each lane takes two sources per step, and
 // the slices are added in order q = 0, 1, .. with cross-lane shuffles.  The
 // kernel shape is a template parameter so every operator evaluates only its
 // nonzero terms.
@@ -257,8 +258,8 @@ __device__ __forceinline__ typename Cx<R>::T kernel_op(R dx, R dy, R dz, R nxx, 
 constexpr int P2P_LIST = 2048;  // source indices of a leaf's near list held in LDS per pass
 
 template <int OPK, typename R>
-__global__ __launch_bounds__(64) void k_p2p(int n_leaf, const int64_t *__restrict__ ts, const int *__restrict__ bptr,
-                                             const int *__restrict__ bsz, const int *__restrict__ ptr,
+__global__ __launch_bounds__(64) void k_p2p(int n_leaf, const int64_t *__restrict__ ts, const int64_t *__restrict__ te,
+                                             const int *__restrict__ ptr,
                                              const int64_t *__restrict__ ss, const int64_t *__restrict__ se,
                                              const PN *__restrict__ pn, double2 *__restrict__ res, double k,
                                              double alpha_im)
@@ -273,10 +274,10 @@ __global__ __launch_bounds__(64) void k_p2p(int n_leaf, const int64_t *__restric
     // the near list's source ranges, concatenated: virtual source v in [0, tot)
     int tot = 0;
     for (int e = e0; e < e1; ++e) tot += (int)(se[e] - ss[e]);
-    int64_t ib = ts[leaf];
-    for (int blk = bptr[leaf]; blk < bptr[leaf + 1]; ib += bsz[blk], ++blk) {
+    const int64_t t1 = te[leaf];
+    for (int64_t ib = ts[leaf]; ib < t1; ib += 64) {
         // lane = t + nt q: target t of the block's nt (<= 64), source slice q of S = 64 / nt
-        const int nt = bsz[blk];
+        const int nt = (int)min((int64_t)64, t1 - ib);
         const int S = 64 / nt;
         const int q = lane / nt, t = lane - q * nt;
         const bool act = q < S;
@@ -1874,42 +1875,21 @@ void device_upload(Plan &P)
     D.n_leaf = (int)P.leaves.size();
     if (P.N >= (int64_t)INT32_MAX) throw std::runtime_error("more points than the near-field kernel indexes (2^31 - 1)");
     {
-        // target blocks: a leaf's targets are cut into blocks of nt targets,
-        // each run with 64 / nt slices of the leaf's concatenated sources, and
-        // the cut minimises the leaf's source steps (sum over blocks of
-        // ceil(n_sources / slices), plus two steps per block); blocks of 64,
-        // 32, 21, 16, .. fill 64, 64, 63, 64, .. lanes where a whole leaf of,
-        // say, 22 targets would leave 20 lanes idle.  Target leaves: the heaviest 2%
-        // by that work first, in decreasing order (one wavefront each), so the
-        // longest wavefronts do not end up in the tail; the rest in tree
-        // order, where neighbouring leaves share sources in L2
+        // target leaves: the heaviest 2% by P2P work first, in decreasing order
+        // (one wavefront each: per block of up to 64 targets, the steps of 64/nt
+        // slices over the concatenated sources), so the longest wavefronts do
+        // not end up in the tail; the rest in tree order, where neighbouring
+        // leaves share sources in L2
         const int nl = (int)P.p2p_tgt_start.size();
-        static const int kBlock[] = {64, 32, 21, 16, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2, 1};
-        constexpr int nB = (int)(sizeof(kBlock) / sizeof(kBlock[0]));
         std::vector<double> work(nl, 0.0);
-        std::vector<std::vector<int>> blocks(nl);
-#pragma omp parallel for schedule(dynamic, 256)
         for (int t = 0; t < nl; ++t) {
-            const int nt_all = (int)(P.p2p_tgt_end[t] - P.p2p_tgt_start[t]);
+            const int64_t nt_all = P.p2p_tgt_end[t] - P.p2p_tgt_start[t];
             int64_t tot = 0;
             for (int e = P.p2p_ptr[t]; e < P.p2p_ptr[t + 1]; ++e) tot += P.p2p_src_end[e] - P.p2p_src_start[e];
-            double cost[nB];
-            for (int b = 0; b < nB; ++b) {
-                const int64_t S = 64 / kBlock[b];
-                cost[b] = 2.0 + (double)((tot + S - 1) / S);  // source steps, plus staging and the slice sum
+            for (int64_t ib = 0; ib < nt_all; ib += 64) {
+                const int64_t S = 64 / std::min<int64_t>(64, nt_all - ib);
+                work[t] += 2.0 + (double)((tot + S - 1) / S);
             }
-            std::vector<double> best(nt_all + 1, 0.0);
-            std::vector<int> pick(nt_all + 1, 0);
-            for (int n = 1; n <= nt_all; ++n) {
-                best[n] = 1e300;
-                for (int b = 0; b < nB; ++b)
-                    if (kBlock[b] <= n && cost[b] + best[n - kBlock[b]] < best[n]) {
-                        best[n] = cost[b] + best[n - kBlock[b]];
-                        pick[n] = kBlock[b];
-                    }
-            }
-            work[t] = best[nt_all];
-            for (int n = nt_all; n > 0; n -= pick[n]) blocks[t].push_back(pick[n]);
         }
         std::vector<int> order(nl);
         for (int t = 0; t < nl; ++t) order[t] = t;
@@ -1922,24 +1902,22 @@ void device_upload(Plan &P)
             for (int t = 0; t < nl; ++t)
                 if (!first[t]) order[q++] = t;
         }
-        std::vector<int64_t> ts(nl), ss, se;
-        std::vector<int> ptr(nl + 1, 0), bptr(nl + 1, 0), bsz;
+        std::vector<int64_t> ts(nl), te(nl), ss, se;
+        std::vector<int> ptr(nl + 1, 0);
         ss.reserve(P.p2p_src_start.size());
         se.reserve(P.p2p_src_end.size());
         for (int q = 0; q < nl; ++q) {
             const int t = order[q];
             ts[q] = P.p2p_tgt_start[t];
+            te[q] = P.p2p_tgt_end[t];
             for (int e = P.p2p_ptr[t]; e < P.p2p_ptr[t + 1]; ++e) {
                 ss.push_back(P.p2p_src_start[e]);
                 se.push_back(P.p2p_src_end[e]);
             }
             ptr[q + 1] = (int)ss.size();
-            bsz.insert(bsz.end(), blocks[t].begin(), blocks[t].end());
-            bptr[q + 1] = (int)bsz.size();
         }
         D.p2p_ts = dupload(D, ts);
-        D.p2p_bptr = dupload(D, bptr);
-        D.p2p_bsz = dupload(D, bsz);
+        D.p2p_te = dupload(D, te);
         D.p2p_ptr = dupload(D, ptr);
         D.p2p_ss = dupload(D, ss);
         D.p2p_se = dupload(D, se);
@@ -2256,13 +2234,13 @@ static void launch_p2p(Plan &P, Device &D, int op, hipStream_t st)
     const dim3 g(D.n_leaf), b(64);
     const double ai = 1.0 / P.opt.alpha_k(P.k);
     if (opk == OPK_H)
-        hipLaunchKernelGGL((k_p2p<OPK_H, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_bptr, D.p2p_bsz, D.p2p_ptr, D.p2p_ss, D.p2p_se,
+        hipLaunchKernelGGL((k_p2p<OPK_H, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
                            (const PN *)D.pn, D.res, P.k, ai);
     else if (opk == OPK_G)
-        hipLaunchKernelGGL((k_p2p<OPK_G, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_bptr, D.p2p_bsz, D.p2p_ptr, D.p2p_ss, D.p2p_se,
+        hipLaunchKernelGGL((k_p2p<OPK_G, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss, D.p2p_se,
                            (const PN *)D.pn, D.res, P.k, ai);
     else
-        hipLaunchKernelGGL((k_p2p<OPK_T1, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_bptr, D.p2p_bsz, D.p2p_ptr, D.p2p_ss,
+        hipLaunchKernelGGL((k_p2p<OPK_T1, R>), g, b, 0, st, D.n_leaf, D.p2p_ts, D.p2p_te, D.p2p_ptr, D.p2p_ss,
                            D.p2p_se, (const PN *)D.pn, D.res, P.k, ai);
 }
 

@@ -91,9 +91,8 @@ struct Device {
     void *pn = nullptr;          // packed positions and normals (64 B per point)
     // near field
     int n_leaf = 0;
-    int64_t *p2p_ts = nullptr, *p2p_ss = nullptr, *p2p_se = nullptr;
+    int64_t *p2p_ts = nullptr, *p2p_te = nullptr, *p2p_ss = nullptr, *p2p_se = nullptr;
     int *p2p_ptr = nullptr;
-    int *p2p_bptr = nullptr, *p2p_bsz = nullptr;   // per leaf: blocks of targets (sizes, in order)
     // templates
     int n_lev = 0;
     int *t_s = nullptr, *t_ny = nullptr;
